@@ -1,0 +1,169 @@
+"""Benchmark of the AES hot path on one MI355X.
+
+One step = key expansion (host) + AES-128 ECB encryption + AES-128 ECB
+decryption + AES-128 CTR over a 1 GiB device-resident buffer of seeded random
+bytes.  ``value`` is payload GB/s over the step (3 GiB of payload per step,
+10^9 bytes per GB).  The dominant kernel's HBM roofline is measured live with
+HIP events on the launch stream; the CPU oracle is timed on a bounded sample
+of the same workload on the host cores.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+       python bench.py --copy-calibration   (plain 1 GiB device copies, for
+                                             scaling HBM byte counters)
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "AES-128 ECB/CTR GB/s at 1 GiB (% HBM roofline); batched GB/s; serve p50/p99"
+HBM_PEAK_GBS = 8000.0
+GIB = 1 << 30
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--bytes", type=int, default=GIB)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-bytes", type=int, default=96 << 20)
+    ap.add_argument("--copy-calibration", action="store_true")
+    return ap.parse_args()
+
+
+def copy_calibration(torch, n_bytes: int, reps: int = 5) -> None:
+    a = torch.randint(0, 256, (n_bytes,), dtype=torch.uint8, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(reps):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {reps} copies of {n_bytes} bytes")
+
+
+def cpu_baseline(sample_bytes: int) -> dict:
+    import numpy as np
+
+    import oracle
+    from paper_1201_0398_amd import workloads
+    threads = min(os.cpu_count() or 1, 16)
+    w = workloads.single_1gib(seed=1, n_bytes=sample_bytes)
+    key = w.keys[128]
+    t0 = time.perf_counter()
+    ct = oracle.ecb_encrypt(key, w.data, threads=threads)
+    pt = oracle.ecb_decrypt(key, ct, threads=threads)
+    ks = oracle.ctr(key, w.nonce, w.ctr0, w.data, threads=threads)
+    dt = time.perf_counter() - t0
+    assert np.array_equal(pt, w.data) and ks.size == w.data.size
+    return {"value": round(3 * sample_bytes / dt / 1e9, 6), "unit": "GB/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"AES-128 ECB encrypt + ECB decrypt + CTR of the first {sample_bytes >> 20} "
+                      f"MiB of the 1 GiB seed-1 workload, literal FIPS-197 oracle, "
+                      f"{threads} threads, {dt:.1f} s"}
+
+
+def main() -> int:
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the AES path "
+              f"shards without communication, and this build measures one GPU's share.",
+              file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    if args.copy_calibration:
+        copy_calibration(torch, args.bytes)
+        return 0
+
+    from paper_1201_0398_amd import aesgpu as A
+    from paper_1201_0398_amd import workloads
+
+    n_bytes = args.bytes
+    log(f"generating {n_bytes} bytes (seed 1)")
+    w = workloads.single_1gib(seed=1, n_bytes=n_bytes)
+    key = bytes(w.keys[128])
+    d_in = torch.from_numpy(w.data).to("cuda")
+    d_ct = torch.empty_like(d_in)
+    d_pt = torch.empty_like(d_in)
+    d_ctr = torch.empty_like(d_in)
+    ctx = A.aesgpu_create()
+    n_blocks = n_bytes // 16
+    stream = torch.cuda.current_stream()
+    names = ["ecb_encrypt", "ecb_decrypt", "ctr_xcrypt"]
+    events = {n: [] for n in names}
+
+    def step(record: bool):
+        k = A.aesgpu_expand_key(key)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)] if record else None
+        if record:
+            ev[0].record(stream)
+        A.aesgpu_ecb_encrypt(ctx, k, d_in, d_ct, n_blocks)
+        if record:
+            ev[1].record(stream)
+        A.aesgpu_ecb_decrypt(ctx, k, d_ct, d_pt, n_blocks)
+        if record:
+            ev[2].record(stream)
+        A.aesgpu_ctr_xcrypt(ctx, k, w.nonce, w.ctr0, d_in, d_ctr, n_bytes)
+        if record:
+            ev[3].record(stream)
+            for i, n in enumerate(names):
+                events[n].append((ev[i], ev[i + 1]))
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    if not torch.equal(d_pt, d_in):
+        raise SystemExit("round trip failed before timing")
+    log(f"timing {args.steps} steps")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_step = 1e3 * dt / args.steps
+    value = 3 * n_bytes / (dt / args.steps) / 1e9
+    kern_ms = {n: float(np.mean([a.elapsed_time(b) for a, b in events[n]])) for n in names}
+    dominant = max(kern_ms, key=kern_ms.get)
+    algo_bytes = 2 * n_bytes  # read + write of the payload per launch
+    achieved = algo_bytes / (kern_ms[dominant] * 1e-3) / 1e9
+    per_kernel = {n: {"ms": round(kern_ms[n], 4),
+                      "GB_s_payload": round(n_bytes / (kern_ms[n] * 1e-3) / 1e9, 1),
+                      "hbm_frac": round(2 * n_bytes / (kern_ms[n] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+                  for n in names}
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": "AES-128 ECB encrypt + ECB decrypt + CTR (nonce||BE32, ctr0=1) of "
+                               f"a {n_bytes >> 20} MiB uniform random device buffer, seed 1",
+                   "payload_bytes_per_step": 3 * n_bytes},
+        "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None},
+        "kernels": per_kernel,
+    }
+    A.aesgpu_destroy(ctx)
+    del d_in, d_ct, d_pt, d_ctr
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle")
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample_bytes)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

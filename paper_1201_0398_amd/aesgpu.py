@@ -1,0 +1,197 @@
+"""ctypes binding of ``libaesgpu.so`` (C ABI declared in ``include/aesgpu.h``).
+
+Functions keep the C names and only marshal arguments: device buffers are
+torch tensors on a HIP device (or raw integer device addresses), streams are
+torch streams (or raw ``hipStream_t`` integers; default: torch's current
+stream).  Every byte of encryption runs in the library's HIP kernels; there is
+no CPU path.  Loading fails loudly when the library has not been built.
+
+torch is imported before the library is loaded so that the process holds one
+HIP runtime: the library's dependency on ``libamdhip64.so.7`` then resolves
+to the copy torch already loaded.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch  # noqa: F401  (must precede loading the HIP library)
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libaesgpu.so")
+
+AESGPU_OK = 0
+AESGPU_EINVAL = -1
+AESGPU_EKEYLEN = -2
+AESGPU_EALIGN = -3
+AESGPU_ECTR_OVERFLOW = -4
+AESGPU_ENOMEM = -5
+AESGPU_EHIP = -6
+AESGPU_EAGAIN = -7
+
+
+class AesgpuError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        msg = _lib.aesgpu_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} ({status})")
+        self.status = status
+
+
+class aesgpu_key(ctypes.Structure):
+    _fields_ = [("key_bits", ctypes.c_uint32), ("nr", ctypes.c_uint32),
+                ("enc", ctypes.c_uint32 * 60), ("dec", ctypes.c_uint32 * 60)]
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
+            f"g.build()'` (hipcc, gfx950).  There is no fallback path.")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, sz, ci = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    kp = ctypes.POINTER(aesgpu_key)
+    sig = {
+        "aesgpu_create": ([ctypes.POINTER(vp), ci], ci),
+        "aesgpu_destroy": ([vp], None),
+        "aesgpu_expand_key": ([u8p, sz, kp], ci),
+        "aesgpu_ecb_encrypt": ([vp, kp, vp, vp, sz, vp], ci),
+        "aesgpu_ecb_decrypt": ([vp, kp, vp, vp, sz, vp], ci),
+        "aesgpu_ctr_xcrypt": ([vp, kp, u8p, ctypes.c_uint32, vp, vp, sz, vp], ci),
+        "aesgpu_ctr_le128_xcrypt": ([vp, kp, u8p, ctypes.c_uint64, vp, vp, sz, vp], ci),
+        "aesgpu_cbc_decrypt": ([vp, kp, u8p, vp, vp, sz, vp], ci),
+        "aesgpu_strerror": ([ci], ctypes.c_char_p),
+        "aesgpu_ctx_num_cus": ([vp], ci),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    return L
+
+
+_lib: ctypes.CDLL | None = None
+_lib = _load()
+
+
+def lib() -> ctypes.CDLL:
+    return _lib
+
+
+def _check(status: int, what: str) -> int:
+    if status != AESGPU_OK:
+        raise AesgpuError(status, what)
+    return status
+
+
+def _ptr(x) -> int | None:
+    """Device address of a tensor (or an integer address as given)."""
+    if x is None:
+        return None
+    if isinstance(x, int):
+        return x
+    if isinstance(x, torch.Tensor):
+        if not x.is_cuda:
+            raise ValueError("buffer must be a device tensor")
+        if not x.is_contiguous():
+            raise ValueError("buffer must be contiguous")
+        return x.data_ptr()
+    raise TypeError(f"expected a device tensor or an address, got {type(x)}")
+
+
+def _nbytes(x) -> int:
+    return x.numel() * x.element_size()
+
+
+def _stream(stream) -> int | None:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _u8buf(b, n: int):
+    raw = bytes(b)
+    if len(raw) != n:
+        raise ValueError(f"expected {n} bytes, got {len(raw)}")
+    return (ctypes.c_uint8 * n).from_buffer_copy(raw)
+
+
+# ---- context and keys --------------------------------------------------------
+
+def aesgpu_create(device: int | None = None) -> ctypes.c_void_p:
+    if device is None:
+        device = torch.cuda.current_device()
+    h = ctypes.c_void_p()
+    _check(_lib.aesgpu_create(ctypes.byref(h), int(device)), "aesgpu_create")
+    return h
+
+
+def aesgpu_destroy(ctx) -> None:
+    _lib.aesgpu_destroy(ctx)
+
+
+def aesgpu_expand_key(key) -> aesgpu_key:
+    raw = bytes(key)
+    k = aesgpu_key()
+    buf = (ctypes.c_uint8 * max(len(raw), 1)).from_buffer_copy(raw or b"\0")
+    _check(_lib.aesgpu_expand_key(buf, len(raw), ctypes.byref(k)), "aesgpu_expand_key")
+    return k
+
+
+def aesgpu_strerror(status: int) -> str:
+    return _lib.aesgpu_strerror(status).decode()
+
+
+def aesgpu_ctx_num_cus(ctx) -> int:
+    return int(_lib.aesgpu_ctx_num_cus(ctx))
+
+
+# ---- single-buffer calls -------------------------------------------------------
+# Each takes the same arguments as its C function; n_blocks / n_bytes default to
+# the size of d_in.  ``check=False`` returns the status instead of raising.
+
+def aesgpu_ecb_encrypt(ctx, key: aesgpu_key, d_in, d_out, n_blocks: int | None = None,
+                       stream=None, check: bool = True) -> int:
+    if n_blocks is None:
+        n_blocks = _nbytes(d_in) // 16
+    st = _lib.aesgpu_ecb_encrypt(ctx, ctypes.byref(key), _ptr(d_in), _ptr(d_out), n_blocks,
+                                 _stream(stream))
+    return _check(st, "aesgpu_ecb_encrypt") if check else st
+
+
+def aesgpu_ecb_decrypt(ctx, key: aesgpu_key, d_in, d_out, n_blocks: int | None = None,
+                       stream=None, check: bool = True) -> int:
+    if n_blocks is None:
+        n_blocks = _nbytes(d_in) // 16
+    st = _lib.aesgpu_ecb_decrypt(ctx, ctypes.byref(key), _ptr(d_in), _ptr(d_out), n_blocks,
+                                 _stream(stream))
+    return _check(st, "aesgpu_ecb_decrypt") if check else st
+
+
+def aesgpu_ctr_xcrypt(ctx, key: aesgpu_key, nonce, ctr0: int, d_in, d_out,
+                      n_bytes: int | None = None, stream=None, check: bool = True) -> int:
+    if n_bytes is None:
+        n_bytes = _nbytes(d_in)
+    st = _lib.aesgpu_ctr_xcrypt(ctx, ctypes.byref(key), _u8buf(nonce, 12), ctr0, _ptr(d_in),
+                                _ptr(d_out), n_bytes, _stream(stream))
+    return _check(st, "aesgpu_ctr_xcrypt") if check else st
+
+
+def aesgpu_ctr_le128_xcrypt(ctx, key: aesgpu_key, iv, index0: int, d_in, d_out,
+                            n_bytes: int | None = None, stream=None, check: bool = True) -> int:
+    if n_bytes is None:
+        n_bytes = _nbytes(d_in)
+    st = _lib.aesgpu_ctr_le128_xcrypt(ctx, ctypes.byref(key), _u8buf(iv, 16), index0,
+                                      _ptr(d_in), _ptr(d_out), n_bytes, _stream(stream))
+    return _check(st, "aesgpu_ctr_le128_xcrypt") if check else st
+
+
+def aesgpu_cbc_decrypt(ctx, key: aesgpu_key, iv, d_in, d_out, n_blocks: int | None = None,
+                       stream=None, check: bool = True) -> int:
+    if n_blocks is None:
+        n_blocks = _nbytes(d_in) // 16
+    st = _lib.aesgpu_cbc_decrypt(ctx, ctypes.byref(key), _u8buf(iv, 16), _ptr(d_in),
+                                 _ptr(d_out), n_blocks, _stream(stream))
+    return _check(st, "aesgpu_cbc_decrypt") if check else st

@@ -1,0 +1,73 @@
+// Internal declarations shared by the host runtime and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "aesgpu.h"
+
+namespace aesgpu {
+
+// Device table image, in 32-bit words, uploaded once per context:
+//   [kTe + 256*k + x]  T_k[x]  = column MixColumns makes from S(x) in row k
+//   [kTd + 256*k + x]  Td_k[x] = column InvMixColumns makes from InvS(x) in row k
+//   [kIs4 + x]         InvS(x) replicated into all four bytes
+//   [kSb4 + x]         S(x) replicated into all four bytes
+constexpr int kTe = 0;
+constexpr int kTd = 1024;
+constexpr int kIs4 = 2048;
+constexpr int kSb4 = 2304;
+constexpr int kTableWords = 2560;
+
+// Round keys as kernel arguments: 15 rounds x 4 little-endian words.
+struct alignas(16) RoundKeys {
+    uint32_t w[60];
+};
+
+// First-round constants of CTR mode.  With counter words 0..2 fixed by the
+// nonce, every output word of round 1 is one table lookup on counter word 3
+// XORed with a constant that depends only on the key and the nonce.
+struct alignas(16) CtrConsts {
+    uint32_t x0[3];   // counter words 0..2 after the initial AddRoundKey
+    uint32_t k03;     // initial round key word 3
+    uint32_t p[4];    // round-1 constants, one per output word
+};
+
+struct HostTables {
+    uint8_t sbox[256];
+    uint8_t inv_sbox[256];
+    uint32_t words[kTableWords];
+};
+
+// Builds the table image from the library's own GF(2^8) arithmetic.
+const HostTables &host_tables();
+
+// InvMixColumns of one little-endian column word (host).
+uint32_t inv_mix_column(uint32_t w);
+
+enum class Op { kEcbEnc, kEcbDec, kCtrBe32, kCtrLe128, kCbcDec };
+
+struct LaunchArgs {
+    Op op;
+    uint32_t nr;
+    const void *in;
+    void *out;
+    uint64_t n_bytes;     // ECB/CBC: 16 * n_blocks
+    const RoundKeys *rk;  // enc keys for encryption/CTR, dec keys for decryption
+    CtrConsts ctr;        // kCtrBe32 only
+    uint32_t ctr0;        // kCtrBe32 only
+    uint32_t iv[4];       // kCtrLe128 (IV words), kCbcDec (IV words)
+    uint64_t index0;      // kCtrLe128
+};
+
+// Enqueues the kernel for `a` on `stream`; returns an AESGPU status.
+int launch(const uint32_t *d_tables, int n_cu, const LaunchArgs &a, hipStream_t stream);
+
+}  // namespace aesgpu
+
+struct aesgpu_ctx {
+    int device;
+    int n_cu;
+    uint32_t *d_tables;
+};

@@ -1,0 +1,304 @@
+// gfx950 kernels for the T-table AES rounds (paper section 2.1, Eq. (1)) and
+// the parallel modes of section 3: ECB both ways, CTR, CBC decryption.
+//
+// Design (CDNA4):
+//  * One 16-byte block per lane per step, loaded and stored with one
+//    global_load/store_dwordx4; a wave touches 1 KiB of contiguous HBM per
+//    instruction.  Each lane carries BPL independent blocks for ILP.
+//  * The four 1 KiB tables live in LDS, replicated 32 times so that lane L
+//    always reads copy L % 32: the bank of every lookup is fixed by the lane,
+//    whatever the data, so random table indices cause no bank conflicts.
+//    Byte address of copy c of T_t[x]:
+//        (t >> 1) * 65536 + x * 256 + (t & 1) * 128 + 4c          (128 KiB)
+//    so one v_perm_b32 forms an address: byte k of the state word goes to
+//    bits 8..15, the lane's per-table base supplies bits 0..7 and 16..23.
+//  * Decryption adds InvS (replicated into all four bytes of a word) at
+//    131072 + x * 128 + 4c, 32 KiB, for the last round: 160 KiB in total.
+//  * Round keys are kernel arguments, so they are loaded once into SGPRs.
+//  * 1024 threads per workgroup and one workgroup per CU (the tables take the
+//    whole LDS); the grid is at most one workgroup per CU and strides over
+//    tiles of 1024 * BPL blocks.
+#include <hip/hip_runtime.h>
+
+#include <cstdlib>
+
+#include "aes_internal.h"
+
+namespace aesgpu {
+namespace {
+
+constexpr int kWG = 1024;
+constexpr uint32_t kFwdWords = 32768;      // replicated T0..T3 (or Td0..Td3)
+constexpr uint32_t kInvSWords = 8192;      // replicated InvS
+constexpr uint32_t kInvSByte = 4 * kFwdWords;
+
+struct Params {
+    const uint4 *in;
+    uint4 *out;
+    uint64_t n_full;        // whole blocks
+    uint32_t tail;          // bytes of a final partial block (CTR only), 0..15
+    uint32_t ctr0;
+    const uint32_t *tables;
+    uint64_t index0;        // LE-128 counter offset
+    uint32_t iv[4];
+    CtrConsts cc;
+    RoundKeys rk;
+};
+
+struct Bases {
+    uint32_t t[4];  // byte address of this lane's copy of T_t[0]
+    uint32_t invs;  // byte address of this lane's copy of InvS[0]
+};
+
+__device__ __forceinline__ Bases lane_bases() {
+    const uint32_t c4 = (threadIdx.x & 31u) * 4u;
+    return {{c4, c4 + 128u, c4 + 65536u, c4 + 65536u + 128u}, kInvSByte + c4};
+}
+
+// a ^ b ^ c in one v_bitop3_b32 (truth table 0x96 is symmetric in its inputs).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
+__device__ __forceinline__ uint32_t lds_at(const uint32_t *lds, uint32_t byte_addr) {
+    return *reinterpret_cast<const uint32_t *>(reinterpret_cast<const char *>(lds) + byte_addr);
+}
+
+// T lookup indexed by byte K of `word`, in the table whose lane base is `base`.
+template <int K>
+__device__ __forceinline__ uint32_t tlook(const uint32_t *lds, uint32_t word, uint32_t base) {
+    // v_perm_b32: result bytes {base.b0, word.bK, base.b2, 0}.
+    const uint32_t addr = __builtin_amdgcn_perm(word, base, 0x0C020000u | ((4u + K) << 8));
+    return lds_at(lds, addr);
+}
+
+// InvS lookup indexed by byte K of `word` (value replicated in all bytes).
+template <int K>
+__device__ __forceinline__ uint32_t islook(const uint32_t *lds, uint32_t word, uint32_t base) {
+    const uint32_t x = (word >> (8 * K)) & 0xFFu;
+    return lds_at(lds, (x << 7) + base);
+}
+
+// Byte 0 of v0, byte 1 of v1, byte 2 of v2 and byte 3 of v3, XORed with k.
+// The two halves have disjoint bytes, so OR-ing them is the same as XOR.
+__device__ __forceinline__ uint32_t merge4_xor(uint32_t v0, uint32_t v1, uint32_t v2, uint32_t v3,
+                                               uint32_t k) {
+    const uint32_t lo = __builtin_amdgcn_perm(v1, v0, 0x0C0C0500u);
+    const uint32_t hi = __builtin_amdgcn_perm(v3, v2, 0x07020C0Cu);
+    return xor3(lo, hi, k);
+}
+
+// One middle round, Eq. (1).  Forward: output word c reads byte k of word
+// (c + k) mod 4.  Inverse (equivalent inverse cipher): word (c - k) mod 4.
+template <bool kInv>
+__device__ __forceinline__ void mid_round(const uint32_t *lds, const Bases &b, uint32_t (&s)[4],
+                                          const uint32_t *k) {
+    uint32_t o[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int i1 = kInv ? (c + 3) & 3 : (c + 1) & 3;
+        const int i2 = (c + 2) & 3;
+        const int i3 = kInv ? (c + 1) & 3 : (c + 3) & 3;
+        o[c] = xor3(xor3(tlook<0>(lds, s[c], b.t[0]), tlook<1>(lds, s[i1], b.t[1]),
+                         tlook<2>(lds, s[i2], b.t[2])),
+                    tlook<3>(lds, s[i3], b.t[3]), k[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] = o[c];
+}
+
+// Last forward round: SubBytes + ShiftRows + AddRoundKey.  The S-box byte is
+// taken from the T tables: T2 holds S(x) in byte 0, T3 in byte 1, T0 in byte
+// 2 and T1 in byte 3.
+__device__ __forceinline__ void last_round_fwd(const uint32_t *lds, const Bases &b,
+                                               uint32_t (&s)[4], const uint32_t *k) {
+    uint32_t o[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        o[c] = merge4_xor(tlook<0>(lds, s[c], b.t[2]), tlook<1>(lds, s[(c + 1) & 3], b.t[3]),
+                          tlook<2>(lds, s[(c + 2) & 3], b.t[0]),
+                          tlook<3>(lds, s[(c + 3) & 3], b.t[1]), k[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] = o[c];
+}
+
+// Last inverse round: InvSubBytes + InvShiftRows + AddRoundKey.
+__device__ __forceinline__ void last_round_inv(const uint32_t *lds, const Bases &b,
+                                               uint32_t (&s)[4], const uint32_t *k) {
+    uint32_t o[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        o[c] = merge4_xor(islook<0>(lds, s[c], b.invs), islook<1>(lds, s[(c + 3) & 3], b.invs),
+                          islook<2>(lds, s[(c + 2) & 3], b.invs),
+                          islook<3>(lds, s[(c + 1) & 3], b.invs), k[c]);
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) s[c] = o[c];
+}
+
+template <bool kInv>
+__device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ g) {
+    const uint32_t *src = g + (kInv ? kTd : kTe);
+    for (uint32_t i = threadIdx.x; i < kFwdWords; i += kWG) {
+        const uint32_t t = ((i >> 14) << 1) | ((i >> 5) & 1u);
+        const uint32_t x = (i >> 6) & 0xFFu;
+        lds[i] = src[t * 256u + x];
+    }
+    if (kInv) {
+        for (uint32_t i = threadIdx.x; i < kInvSWords; i += kWG) lds[kFwdWords + i] = g[kIs4 + (i >> 5)];
+    }
+    __syncthreads();
+}
+
+__device__ __forceinline__ uint32_t bswap32(uint32_t v) {
+    return __builtin_amdgcn_perm(v, v, 0x00010203u);
+}
+
+template <Op OP, int NR, int BPL>
+__global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
+    constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
+    __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords];
+    stage_tables<kInv>(lds, p.tables);
+    const Bases b = lane_bases();
+
+    const uint64_t n_total = p.n_full + (p.tail ? 1 : 0);
+    const uint64_t tile = uint64_t(kWG) * BPL;
+    for (uint64_t base = uint64_t(blockIdx.x) * tile; base < n_total;
+         base += uint64_t(gridDim.x) * tile) {
+        uint32_t s[BPL][4];
+        uint4 in[BPL];
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+            const uint64_t idx = base + uint64_t(j) * kWG + threadIdx.x;
+            in[j] = make_uint4(0, 0, 0, 0);
+            if (idx < p.n_full) in[j] = p.in[idx];
+            if constexpr (OP == Op::kEcbEnc || OP == Op::kEcbDec || OP == Op::kCbcDec) {
+                s[j][0] = in[j].x ^ p.rk.w[0];
+                s[j][1] = in[j].y ^ p.rk.w[1];
+                s[j][2] = in[j].z ^ p.rk.w[2];
+                s[j][3] = in[j].w ^ p.rk.w[3];
+            } else if constexpr (OP == Op::kCtrBe32) {
+                // Counter block: nonce words 0..2, word 3 = BE32(ctr0 + idx).
+                // Round 1 is done here: output word c needs one lookup, on
+                // byte (3 - c) of word 3; the other three terms are constants.
+                const uint32_t w3 = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.k03;
+                s[j][0] = p.cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
+                s[j][1] = p.cc.p[1] ^ tlook<2>(lds, w3, b.t[2]);
+                s[j][2] = p.cc.p[2] ^ tlook<1>(lds, w3, b.t[1]);
+                s[j][3] = p.cc.p[3] ^ tlook<0>(lds, w3, b.t[0]);
+            } else {  // kCtrLe128: IV + index0 + idx as a 128-bit LE integer
+                const uint64_t add = p.index0 + idx;
+                const uint64_t lo0 = uint64_t(p.iv[0]) | (uint64_t(p.iv[1]) << 32);
+                const uint64_t hi0 = uint64_t(p.iv[2]) | (uint64_t(p.iv[3]) << 32);
+                const uint64_t lo = lo0 + add;
+                const uint64_t hi = hi0 + (lo < lo0 ? 1u : 0u);
+                s[j][0] = uint32_t(lo) ^ p.rk.w[0];
+                s[j][1] = uint32_t(lo >> 32) ^ p.rk.w[1];
+                s[j][2] = uint32_t(hi) ^ p.rk.w[2];
+                s[j][3] = uint32_t(hi >> 32) ^ p.rk.w[3];
+            }
+        }
+        const int first = (OP == Op::kCtrBe32) ? 2 : 1;
+#pragma unroll
+        for (int r = 1; r < NR; ++r) {
+            if (r < first) continue;
+#pragma unroll
+            for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], &p.rk.w[4 * r]);
+        }
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+            if (kInv)
+                last_round_inv(lds, b, s[j], &p.rk.w[4 * NR]);
+            else
+                last_round_fwd(lds, b, s[j], &p.rk.w[4 * NR]);
+        }
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
+            const uint64_t idx = base + uint64_t(j) * kWG + threadIdx.x;
+            uint4 o = make_uint4(s[j][0], s[j][1], s[j][2], s[j][3]);
+            if constexpr (OP == Op::kCtrBe32 || OP == Op::kCtrLe128) {
+                o.x ^= in[j].x;
+                o.y ^= in[j].y;
+                o.z ^= in[j].z;
+                o.w ^= in[j].w;
+            } else if constexpr (OP == Op::kCbcDec) {
+                // Eq. (2): XOR with the previous ciphertext block (IV first).
+                uint4 prev = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
+                if (idx > 0 && idx < p.n_full) prev = p.in[idx - 1];
+                o.x ^= prev.x;
+                o.y ^= prev.y;
+                o.z ^= prev.z;
+                o.w ^= prev.w;
+            }
+            if (idx < p.n_full) {
+                p.out[idx] = o;
+            } else if (idx == p.n_full && p.tail) {
+                // Partial last block of a CTR call: byte-wise, only in range.
+                const uint8_t *src = reinterpret_cast<const uint8_t *>(p.in + p.n_full);
+                uint8_t *dst = reinterpret_cast<uint8_t *>(p.out + p.n_full);
+                const uint32_t ks[4] = {s[j][0], s[j][1], s[j][2], s[j][3]};
+                for (uint32_t q = 0; q < p.tail; ++q)
+                    dst[q] = src[q] ^ uint8_t(ks[q >> 2] >> (8 * (q & 3)));
+            }
+        }
+    }
+}
+
+template <Op OP, int NR, int BPL>
+int launch_one(const Params &p, int n_cu, hipStream_t stream) {
+    const uint64_t n_total = p.n_full + (p.tail ? 1 : 0);
+    const uint64_t tiles = (n_total + uint64_t(kWG) * BPL - 1) / (uint64_t(kWG) * BPL);
+    const uint32_t grid = uint32_t(tiles < uint64_t(n_cu) ? tiles : uint64_t(n_cu));
+    hipLaunchKernelGGL((aes_kernel<OP, NR, BPL>), dim3(grid), dim3(kWG), 0, stream, p);
+    return hipGetLastError() == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
+}
+
+template <Op OP, int BPL>
+int launch_nr(const Params &p, uint32_t nr, int n_cu, hipStream_t stream) {
+    switch (nr) {
+        case 10: return launch_one<OP, 10, BPL>(p, n_cu, stream);
+        case 12: return launch_one<OP, 12, BPL>(p, n_cu, stream);
+        case 14: return launch_one<OP, 14, BPL>(p, n_cu, stream);
+        default: return AESGPU_EINVAL;
+    }
+}
+
+template <Op OP>
+int launch_op(const Params &p, uint32_t nr, int n_cu, hipStream_t stream) {
+    static const int forced = [] {
+        const char *e = std::getenv("AESGPU_FORCE_BPL");
+        return e ? std::atoi(e) : 0;
+    }();
+    switch (forced) {
+        case 1: return launch_nr<OP, 1>(p, nr, n_cu, stream);
+        case 2: return launch_nr<OP, 2>(p, nr, n_cu, stream);
+        default: return launch_nr<OP, 4>(p, nr, n_cu, stream);
+    }
+}
+
+}  // namespace
+
+int launch(const uint32_t *d_tables, int n_cu, const LaunchArgs &a, hipStream_t stream) {
+    Params p{};
+    p.in = static_cast<const uint4 *>(a.in);
+    p.out = static_cast<uint4 *>(a.out);
+    p.n_full = a.n_bytes / 16;
+    p.tail = uint32_t(a.n_bytes % 16);
+    p.ctr0 = a.ctr0;
+    p.tables = d_tables;
+    p.index0 = a.index0;
+    for (int i = 0; i < 4; ++i) p.iv[i] = a.iv[i];
+    p.cc = a.ctr;
+    p.rk = *a.rk;
+    switch (a.op) {
+        case Op::kEcbEnc: return launch_op<Op::kEcbEnc>(p, a.nr, n_cu, stream);
+        case Op::kEcbDec: return launch_op<Op::kEcbDec>(p, a.nr, n_cu, stream);
+        case Op::kCtrBe32: return launch_op<Op::kCtrBe32>(p, a.nr, n_cu, stream);
+        case Op::kCtrLe128: return launch_op<Op::kCtrLe128>(p, a.nr, n_cu, stream);
+        case Op::kCbcDec: return launch_op<Op::kCbcDec>(p, a.nr, n_cu, stream);
+    }
+    return AESGPU_EINVAL;
+}
+
+}  // namespace aesgpu
