@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bytes", type=int, default=96 << 20)
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-reps", type=int, default=5)
     return ap.parse_args()
 
 
@@ -50,6 +52,67 @@ def copy_calibration(torch, n_bytes: int, reps: int = 5) -> None:
         b.copy_(a)
     torch.cuda.synchronize()
     log(f"copy calibration: {reps} copies of {n_bytes} bytes")
+
+
+def time_call(torch, fn, reps: int) -> float:
+    """Mean seconds per call, HIP events on the current stream."""
+    fn()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    b.synchronize()
+    return a.elapsed_time(b) * 1e-3 / reps
+
+
+def single_rates(torch, A, ctx, w, d_in, d_out, reps: int = 3) -> dict:
+    """Single-buffer payload rates (bytes/s) per (key bits, mode) over d_in."""
+    n = d_in.numel()
+    rates = {}
+    for bits in (128, 192, 256):
+        k = A.aesgpu_expand_key(bytes(w.keys[bits]))
+        rates[(bits, "ecb_enc")] = n / time_call(
+            torch, lambda: A.aesgpu_ecb_encrypt(ctx, k, d_in, d_out), reps)
+        rates[(bits, "ecb_dec")] = n / time_call(
+            torch, lambda: A.aesgpu_ecb_decrypt(ctx, k, d_in, d_out), reps)
+        rates[(bits, "ctr")] = n / time_call(
+            torch, lambda: A.aesgpu_ctr_xcrypt(ctx, k, w.nonce, 1, d_in, d_out), reps)
+    return rates
+
+
+def batched_bench(torch, A, ctx, rates: dict, reps: int) -> dict:
+    """The 65,536-message batch (seed 3), encrypt direction, graph replays."""
+    import numpy as np
+
+    from paper_1201_0398_amd import workloads
+    log("generating the batched workload (seed 3)")
+    w = workloads.batched(seed=3)
+    m = w.lengths.size
+    msgs = A.make_msgs(w.offsets, w.offsets, w.lengths, np.arange(m), w.key_bits, w.modes,
+                       np.zeros(m, dtype=np.int64), w.nonces, w.ctr0)
+    plan = A.aesgpu_batch_plan(ctx, msgs)
+    info = A.aesgpu_batch_info(plan)
+    d_keys = torch.from_numpy(w.keys.reshape(-1).copy()).to("cuda")
+    d_in = torch.from_numpy(w.data.copy()).to("cuda")
+    d_out = torch.empty_like(d_in)
+    log(f"timing the batch: {m} messages, {w.total_bytes} bytes")
+    sec = time_call(torch, lambda: A.aesgpu_batch_run(plan, d_keys, m, d_in, d_out), reps)
+    # Reference time: every message at the single-buffer rate of its key size and mode.
+    t_ref = sum(float(w.lengths[(w.key_bits == bits) & (w.modes == mode)].sum()) /
+                rates[(bits, "ctr" if mode else "ecb_enc")]
+                for bits in (128, 192, 256) for mode in (0, 1))
+    t_128 = w.total_bytes / rates[(128, "ecb_enc")]
+    A.aesgpu_batch_free(plan)
+    return {"GB_s": round(w.total_bytes / sec / 1e9, 1), "ms": round(sec * 1e3, 3),
+            "messages": m, "bytes": int(w.total_bytes),
+            "tiles": int(info.n_tiles_forward + info.n_tiles_inverse),
+            "tile_blocks": int(info.tile_blocks), "blocks_per_lane": int(info.blocks_per_lane),
+            "time_vs_single_buffer_mix": round(sec / t_ref, 3),
+            "time_vs_single_buffer_aes128_ecb": round(sec / t_128, 3),
+            "workload": "65,536 messages, log-uniform 16 B..1 MiB, own key each, key size "
+                        "uniform over 128/192/256, ECB or CTR 50/50, encrypt, seed 3; one "
+                        "persistent launch with device key expansion, hipGraph replay"}
 
 
 def cpu_baseline(sample_bytes: int) -> dict:
@@ -156,8 +219,13 @@ def main() -> int:
                      "traffic": None},
         "kernels": per_kernel,
     }
+    if not args.no_batched:
+        rates = single_rates(torch, A, ctx, w, d_in, d_ct)
+        out["single_buffer_GB_s"] = {f"aes{b}_{m}": round(v / 1e9, 1) for (b, m), v in rates.items()}
+        del d_pt, d_ctr
+        out["batched"] = batched_bench(torch, A, ctx, rates, args.batched_reps)
     A.aesgpu_destroy(ctx)
-    del d_in, d_ct, d_pt, d_ctr
+    del d_in, d_ct
     if not args.no_cpu_baseline:
         log("timing the CPU oracle")
         out["cpu_baseline"] = cpu_baseline(args.cpu_sample_bytes)

@@ -140,6 +140,92 @@ int aesgpu_ctr_le128_xcrypt(aesgpu_ctx *ctx, const aesgpu_key *key, const uint8_
 int aesgpu_cbc_decrypt(aesgpu_ctx *ctx, const aesgpu_key *key, const uint8_t *iv,
                        const void *d_in, void *d_out, size_t n_blocks, aesgpu_stream_t stream);
 
+/* ------------------------------------------------------------------------ */
+/* Batched messages: one persistent launch per table set                     */
+/* ------------------------------------------------------------------------ */
+
+enum { AESGPU_MODE_ECB = 0, AESGPU_MODE_CTR = 1 };
+enum { AESGPU_DIR_ENCRYPT = 0, AESGPU_DIR_DECRYPT = 1 };
+
+/*
+ * One message of a batch (host struct, 48 bytes).  Its input is
+ * d_in + in_off and its output d_out + out_off (both 16-byte aligned), its key
+ * the raw key bytes at d_keys + 32 * key_slot.  ECB messages are whole blocks
+ * and use `dir`; CTR messages (nonce || BE32(ctr0 + i), as
+ * aesgpu_ctr_xcrypt()) may end in a partial block and ignore `dir`.
+ */
+typedef struct {
+    uint64_t in_off;
+    uint64_t out_off;
+    uint64_t n_bytes;
+    uint32_t key_slot;
+    uint16_t key_bits;   /* 128, 192 or 256 */
+    uint8_t mode;        /* AESGPU_MODE_ECB or AESGPU_MODE_CTR */
+    uint8_t dir;         /* AESGPU_DIR_ENCRYPT or AESGPU_DIR_DECRYPT */
+    uint8_t nonce[12];
+    uint32_t ctr0;
+} aesgpu_msg;
+
+#define AESGPU_BATCH_NO_GRAPH 1u /* enqueue the launches directly, no hipGraph */
+
+/* Launch shape of a batch; zero fields take the defaults (4 blocks per lane,
+ * 2048-block tiles).  tile_blocks must be a multiple of 64 * blocks_per_lane. */
+typedef struct {
+    uint32_t blocks_per_lane; /* 2 or 4 */
+    uint32_t tile_blocks;
+    uint32_t flags;           /* AESGPU_BATCH_* */
+} aesgpu_batch_config;
+
+typedef struct {
+    uint64_t n_msgs;
+    uint64_t n_tiles_forward;  /* ECB-encrypt and CTR tiles */
+    uint64_t n_tiles_inverse;  /* ECB-decrypt tiles */
+    uint64_t total_bytes;      /* sum of n_bytes */
+    uint64_t in_bytes_needed;  /* max(in_off + n_bytes) */
+    uint64_t out_bytes_needed; /* max(out_off + n_bytes) */
+    uint32_t blocks_per_lane;
+    uint32_t tile_blocks;
+    uint32_t launches;         /* persistent launches per run (0, 1 or 2) */
+} aesgpu_batch_stats;
+
+typedef struct aesgpu_batch aesgpu_batch;
+
+/*
+ * Plans a batch of m messages (the paper's per-pixel independence, section 3,
+ * applied across messages): validates every message, cuts them into
+ * message-pure tiles, sorts each queue longest first and copies the
+ * descriptors to the device (synchronously).  cfg may be NULL.  The plan
+ * holds device memory until aesgpu_batch_free().  Errors: EINVAL (bad mode,
+ * direction, config, ECB length not a multiple of 16), EKEYLEN (key_bits),
+ * EALIGN (offsets), ECTR_OVERFLOW, ENOMEM, EHIP.
+ */
+int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
+                      const aesgpu_batch_config *cfg, aesgpu_batch **out);
+
+/*
+ * Runs a planned batch on `stream`: every message is encrypted or decrypted
+ * with its own key, expanded on the device inside the launch (FIPS-197
+ * KeyExpansion, plus the equivalent-inverse-cipher keys for ECB decryption).
+ * d_keys holds n_key_slots raw keys at a 32-byte stride (key bytes first);
+ * d_in and d_out are in_bytes / out_bytes long and must hold every message
+ * (EINVAL otherwise).  d_in == d_out runs in place; other overlap is EINVAL.
+ * Messages whose outputs overlap each other give undefined output.  By
+ * default the launches are captured once into a hipGraph and replayed; the
+ * graph is re-captured when d_keys, d_in or d_out change.  Calls on one plan
+ * must not overlap in time (they share the plan's tile counters).
+ * Errors: EINVAL, EALIGN, EHIP.
+ */
+int aesgpu_batch_run(aesgpu_batch *plan, const uint8_t *d_keys, size_t n_key_slots,
+                     const void *d_in, size_t in_bytes, void *d_out, size_t out_bytes,
+                     aesgpu_stream_t stream);
+
+/* Plan statistics (host only).  Errors: EINVAL. */
+int aesgpu_batch_info(const aesgpu_batch *plan, aesgpu_batch_stats *out);
+
+/* Frees the plan (device descriptors, graph).  NULL is ignored.  The caller
+ * must make sure no run of the plan is still executing. */
+void aesgpu_batch_free(aesgpu_batch *plan);
+
 /* Human-readable name of a status code (static string, never NULL). */
 const char *aesgpu_strerror(int status);
 

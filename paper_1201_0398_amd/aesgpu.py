@@ -42,6 +42,36 @@ class aesgpu_key(ctypes.Structure):
                 ("enc", ctypes.c_uint32 * 60), ("dec", ctypes.c_uint32 * 60)]
 
 
+AESGPU_MODE_ECB = 0
+AESGPU_MODE_CTR = 1
+AESGPU_DIR_ENCRYPT = 0
+AESGPU_DIR_DECRYPT = 1
+AESGPU_BATCH_NO_GRAPH = 1
+
+
+class aesgpu_msg(ctypes.Structure):
+    _fields_ = [("in_off", ctypes.c_uint64), ("out_off", ctypes.c_uint64),
+                ("n_bytes", ctypes.c_uint64), ("key_slot", ctypes.c_uint32),
+                ("key_bits", ctypes.c_uint16), ("mode", ctypes.c_uint8), ("dir", ctypes.c_uint8),
+                ("nonce", ctypes.c_uint8 * 12), ("ctr0", ctypes.c_uint32)]
+
+
+class aesgpu_batch_config(ctypes.Structure):
+    _fields_ = [("blocks_per_lane", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
+
+
+class aesgpu_batch_stats(ctypes.Structure):
+    _fields_ = [("n_msgs", ctypes.c_uint64), ("n_tiles_forward", ctypes.c_uint64),
+                ("n_tiles_inverse", ctypes.c_uint64), ("total_bytes", ctypes.c_uint64),
+                ("in_bytes_needed", ctypes.c_uint64), ("out_bytes_needed", ctypes.c_uint64),
+                ("blocks_per_lane", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
+                ("launches", ctypes.c_uint32)]
+
+
+assert ctypes.sizeof(aesgpu_msg) == 48
+
+
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(
@@ -60,6 +90,11 @@ def _load() -> ctypes.CDLL:
         "aesgpu_ctr_xcrypt": ([vp, kp, u8p, ctypes.c_uint32, vp, vp, sz, vp], ci),
         "aesgpu_ctr_le128_xcrypt": ([vp, kp, u8p, ctypes.c_uint64, vp, vp, sz, vp], ci),
         "aesgpu_cbc_decrypt": ([vp, kp, u8p, vp, vp, sz, vp], ci),
+        "aesgpu_batch_plan": ([vp, ctypes.POINTER(aesgpu_msg), sz,
+                               ctypes.POINTER(aesgpu_batch_config), ctypes.POINTER(vp)], ci),
+        "aesgpu_batch_run": ([vp, vp, sz, vp, sz, vp, sz, vp], ci),
+        "aesgpu_batch_info": ([vp, ctypes.POINTER(aesgpu_batch_stats)], ci),
+        "aesgpu_batch_free": ([vp], None),
         "aesgpu_strerror": ([ci], ctypes.c_char_p),
         "aesgpu_ctx_num_cus": ([vp], ci),
     }
@@ -195,3 +230,61 @@ def aesgpu_cbc_decrypt(ctx, key: aesgpu_key, iv, d_in, d_out, n_blocks: int | No
     st = _lib.aesgpu_cbc_decrypt(ctx, ctypes.byref(key), _u8buf(iv, 16), _ptr(d_in),
                                  _ptr(d_out), n_blocks, _stream(stream))
     return _check(st, "aesgpu_cbc_decrypt") if check else st
+
+
+# ---- batched messages ------------------------------------------------------------
+
+def make_msgs(in_off, out_off, n_bytes, key_slot, key_bits, mode, dir, nonce=None, ctr0=None):
+    """Array of ``aesgpu_msg`` from per-message sequences (numpy or lists);
+    ``nonce`` is an (m, 12) uint8 array."""
+    import numpy as np
+    m = len(n_bytes)
+    arr = (aesgpu_msg * m)()
+    raw = np.frombuffer(arr, dtype=np.uint8).reshape(m, 48)
+    view = raw.view(np.dtype([("in_off", "<u8"), ("out_off", "<u8"), ("n_bytes", "<u8"),
+                              ("key_slot", "<u4"), ("key_bits", "<u2"), ("mode", "u1"),
+                              ("dir", "u1"), ("nonce", "u1", (12,)), ("ctr0", "<u4")])).reshape(m)
+    view["in_off"] = in_off
+    view["out_off"] = out_off
+    view["n_bytes"] = n_bytes
+    view["key_slot"] = key_slot
+    view["key_bits"] = key_bits
+    view["mode"] = mode
+    view["dir"] = dir
+    if nonce is not None:
+        view["nonce"] = nonce
+    view["ctr0"] = 1 if ctr0 is None else ctr0
+    return arr
+
+
+def aesgpu_batch_plan(ctx, msgs, blocks_per_lane: int = 0, tile_blocks: int = 0,
+                      flags: int = 0, check: bool = True):
+    """Returns a plan handle (or the status when ``check`` is False and it fails)."""
+    cfg = aesgpu_batch_config(blocks_per_lane, tile_blocks, flags)
+    h = ctypes.c_void_p()
+    st = _lib.aesgpu_batch_plan(ctx, msgs, len(msgs), ctypes.byref(cfg), ctypes.byref(h))
+    if check:
+        _check(st, "aesgpu_batch_plan")
+        return h
+    return h if st == AESGPU_OK else st
+
+
+def aesgpu_batch_run(plan, d_keys, n_key_slots: int, d_in, d_out, in_bytes: int | None = None,
+                     out_bytes: int | None = None, stream=None, check: bool = True) -> int:
+    if in_bytes is None:
+        in_bytes = _nbytes(d_in)
+    if out_bytes is None:
+        out_bytes = _nbytes(d_out)
+    st = _lib.aesgpu_batch_run(plan, _ptr(d_keys), n_key_slots, _ptr(d_in), in_bytes,
+                               _ptr(d_out), out_bytes, _stream(stream))
+    return _check(st, "aesgpu_batch_run") if check else st
+
+
+def aesgpu_batch_info(plan) -> aesgpu_batch_stats:
+    st = aesgpu_batch_stats()
+    _check(_lib.aesgpu_batch_info(plan, ctypes.byref(st)), "aesgpu_batch_info")
+    return st
+
+
+def aesgpu_batch_free(plan) -> None:
+    _lib.aesgpu_batch_free(plan)

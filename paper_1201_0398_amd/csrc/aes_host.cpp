@@ -63,8 +63,7 @@ HostTables build_tables() {
             t.words[kTe + 256 * k + x] = rotl32(te0, 8 * k);
             t.words[kTd + 256 * k + x] = rotl32(td0, 8 * k);
         }
-        t.words[kIs4 + x] = 0x01010101u * si;
-        t.words[kSb4 + x] = 0x01010101u * s;
+        t.words[kInvSS + x] = uint32_t(si) | (uint32_t(s) << 8);
     }
     return t;
 }

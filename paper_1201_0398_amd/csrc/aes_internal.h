@@ -12,13 +12,12 @@ namespace aesgpu {
 // Device table image, in 32-bit words, uploaded once per context:
 //   [kTe + 256*k + x]  T_k[x]  = column MixColumns makes from S(x) in row k
 //   [kTd + 256*k + x]  Td_k[x] = column InvMixColumns makes from InvS(x) in row k
-//   [kIs4 + x]         InvS(x) replicated into all four bytes
-//   [kSb4 + x]         S(x) replicated into all four bytes
+//   [kInvSS + x]       InvS(x) in byte 0 and S(x) in byte 1
 constexpr int kTe = 0;
 constexpr int kTd = 1024;
-constexpr int kIs4 = 2048;
-constexpr int kSb4 = 2304;
-constexpr int kTableWords = 2560;
+constexpr int kInvSS = 2048;
+
+constexpr int kTableWords = 2304;
 
 // Round keys as kernel arguments: 15 rounds x 4 little-endian words.
 struct alignas(16) RoundKeys {
