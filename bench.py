@@ -27,6 +27,32 @@ HBM_PEAK_GBS = 8000.0
 GIB = 1 << 30
 
 
+HBM_SUMMARY = os.path.join(ROOT, "profiles", "aes128_1gib_hbm_bytes.md")
+KERNEL_SOURCES = ["aes_kernels.hip", "aes_device.h", "aes_internal.h"]
+
+
+def measured_traffic(kernel: str, n_bytes: int):
+    """HBM bytes per launch from the committed rocprofv3 summary (FETCH_SIZE +
+    WRITE_SIZE scaled by a plain copy), or None when the kernel sources have
+    changed since the counters were taken or the workload size differs."""
+    import hashlib
+    if n_bytes != GIB or not os.path.exists(HBM_SUMMARY):
+        return None
+    h = hashlib.sha256(b"".join(
+        open(os.path.join(ROOT, "paper_1201_0398_amd", "csrc", f), "rb").read()
+        for f in KERNEL_SOURCES)).hexdigest()
+    vals = {}
+    for line in open(HBM_SUMMARY):
+        if line.startswith("kernel_source_sha256:"):
+            vals["sha"] = line.split(":", 1)[1].strip()
+        elif line.startswith("traffic_bytes_per_launch"):
+            name, v = line[len("traffic_bytes_per_launch"):].split(":")
+            vals[name.strip()] = int(float(v))
+    if vals.get("sha") != h:
+        return None
+    return vals.get(kernel)
+
+
 def log(msg: str) -> None:
     print(msg, file=sys.stderr, flush=True)
 
@@ -42,6 +68,8 @@ def parse():
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=100000)
     return ap.parse_args()
 
 
@@ -113,6 +141,54 @@ def batched_bench(torch, A, ctx, rates: dict, reps: int) -> dict:
             "workload": "65,536 messages, log-uniform 16 B..1 MiB, own key each, key size "
                         "uniform over 128/192/256, ECB or CTR 50/50, encrypt, seed 3; one "
                         "persistent launch with device key expansion, hipGraph replay"}
+
+
+def serving_bench(torch, A, ctx, n_requests: int) -> dict:
+    """Poisson arrivals of ECB requests (64 B..16 MiB log-uniform, half encrypt,
+    half decrypt, keys from a resident pool of 1,024), replayed natively
+    against the continuous-batching server at fractions of its measured
+    saturation rate."""
+    import numpy as np
+
+    from paper_1201_0398_amd import workloads
+    arena = 4 << 30
+    tr = workloads.serving(rate_per_s=1.0, n_requests=n_requests, seed=4, source_bytes=1 << 28)
+    std_gaps = np.diff(np.concatenate([[0.0], tr.arrivals]))  # Exp(1) gaps: scale per rate
+    total = int(tr.sizes.sum())
+    src = torch.from_numpy(tr.source.copy()).to("cuda")
+    ptrs = src.data_ptr() + tr.src_offsets
+    server = A.aesgpu_server_create(ctx, tr.pool_keys, tr.pool_bits, arena_bytes=arena)
+
+    def replay(arrivals):
+        reqs = A.make_requests(arrivals, ptrs, tr.sizes, tr.key_ids, tr.dirs)
+        t0 = A.aesgpu_server_now(server) + 0.002
+        done = A.aesgpu_server_replay(server, reqs, t0)
+        t = np.array([(d.t_arrival, d.t_done) for d in done])
+        lat = t[:, 1] - t[:, 0]
+        span = t[:, 1].max() - t0
+        return lat, span
+
+    replay(np.zeros(n_requests))  # warm-up
+    lat, span = replay(np.zeros(n_requests))
+    lam_sat = n_requests / span
+    points = []
+    for frac in (0.1, 0.25, 0.5, 0.7, 0.85, 0.95):
+        lam = frac * lam_sat
+        lat, span = replay(np.cumsum(std_gaps / lam))
+        points.append({"frac_of_saturation": frac, "rate_req_s": round(lam, 1),
+                       "p50_us": round(float(np.median(lat)) * 1e6, 1),
+                       "p99_us": round(float(np.quantile(lat, 0.99)) * 1e6, 1),
+                       "GB_s": round(total / span / 1e9, 1)})
+        log(f"serving at {frac:.2f} of saturation: {points[-1]}")
+    st = A.aesgpu_server_get_stats(server)
+    A.aesgpu_server_destroy(server)
+    return {"saturation_GB_s": round(total / (n_requests / lam_sat) / 1e9, 1),
+            "saturation_req_s": round(lam_sat, 1), "requests_per_point": n_requests,
+            "mean_request_bytes": round(total / n_requests, 1), "arena_bytes": arena,
+            "batches": int(st.batches), "points": points,
+            "workload": "Poisson arrivals, ECB requests 64 B..16 MiB log-uniform, 50/50 "
+                        "encrypt/decrypt, 1,024 resident keys of mixed size, seed 4; inputs "
+                        "device-resident; latency = completion seen by the host - arrival"}
 
 
 def cpu_baseline(sample_bytes: int) -> dict:
@@ -216,7 +292,11 @@ def main() -> int:
                    "payload_bytes_per_step": 3 * n_bytes},
         "roofline": {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic(dominant, n_bytes),
+                     "algorithmic_bytes": algo_bytes,
+                     "note": "32 B of HBM per 16-B block; the kernel is bound by LDS table-read "
+                             "issue (160 random reads per AES-128 block, 2 LDS cycles per wave64 "
+                             "read), see profiles/aes128_1gib_lds_valu_counters.md"},
         "kernels": per_kernel,
     }
     if not args.no_batched:
@@ -224,6 +304,8 @@ def main() -> int:
         out["single_buffer_GB_s"] = {f"aes{b}_{m}": round(v / 1e9, 1) for (b, m), v in rates.items()}
         del d_pt, d_ctr
         out["batched"] = batched_bench(torch, A, ctx, rates, args.batched_reps)
+    if not args.no_serving:
+        out["serving"] = serving_bench(torch, A, ctx, args.serve_requests)
     A.aesgpu_destroy(ctx)
     del d_in, d_ct
     if not args.no_cpu_baseline:

@@ -168,10 +168,10 @@ typedef struct {
 
 #define AESGPU_BATCH_NO_GRAPH 1u /* enqueue the launches directly, no hipGraph */
 
-/* Launch shape of a batch; zero fields take the defaults (4 blocks per lane,
- * 2048-block tiles).  tile_blocks must be a multiple of 64 * blocks_per_lane. */
+/* Launch shape of a batch; zero fields take the defaults (2 blocks per lane,
+ * 8192-block tiles).  tile_blocks must be a multiple of 64 * blocks_per_lane. */
 typedef struct {
-    uint32_t blocks_per_lane; /* 2 or 4 */
+    uint32_t blocks_per_lane; /* 1 or 2 */
     uint32_t tile_blocks;
     uint32_t flags;           /* AESGPU_BATCH_* */
 } aesgpu_batch_config;
@@ -185,7 +185,7 @@ typedef struct {
     uint64_t out_bytes_needed; /* max(out_off + n_bytes) */
     uint32_t blocks_per_lane;
     uint32_t tile_blocks;
-    uint32_t launches;         /* persistent launches per run (0, 1 or 2) */
+    uint32_t launches;         /* persistent launches per run (0 or 1) */
 } aesgpu_batch_stats;
 
 typedef struct aesgpu_batch aesgpu_batch;
@@ -225,6 +225,129 @@ int aesgpu_batch_info(const aesgpu_batch *plan, aesgpu_batch_stats *out);
 /* Frees the plan (device descriptors, graph).  NULL is ignored.  The caller
  * must make sure no run of the plan is still executing. */
 void aesgpu_batch_free(aesgpu_batch *plan);
+
+/* ------------------------------------------------------------------------ */
+/* Device-memory range allocator (host bookkeeping only)                    */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * First-fit allocator of byte ranges [0, capacity) with coalescing on
+ * release, in multiples of `granule` (a power of two dividing capacity).  It
+ * only does the bookkeeping (no device memory is touched); the server admits
+ * requests with it.  Not thread-safe.  Errors: EINVAL (bad sizes, a release
+ * that is not a live allocation), ENOMEM; aesgpu_arena_alloc returns EAGAIN
+ * when no free range is large enough right now and EINVAL when the request
+ * exceeds the capacity.
+ */
+typedef struct aesgpu_arena aesgpu_arena;
+int aesgpu_arena_create(uint64_t capacity, uint64_t granule, aesgpu_arena **out);
+int aesgpu_arena_alloc(aesgpu_arena *arena, uint64_t n_bytes, uint64_t *offset);
+int aesgpu_arena_release(aesgpu_arena *arena, uint64_t offset, uint64_t n_bytes);
+int aesgpu_arena_query(const aesgpu_arena *arena, uint64_t *used, uint64_t *largest_free,
+                       uint64_t *high_water);
+void aesgpu_arena_destroy(aesgpu_arena *arena);
+
+/* ------------------------------------------------------------------------ */
+/* Continuous-batching server                                               */
+/* ------------------------------------------------------------------------ */
+
+typedef struct aesgpu_server aesgpu_server;
+
+typedef struct {
+    uint64_t arena_bytes;        /* device memory for request outputs (multiple of 256) */
+    uint32_t n_streams;          /* batches in flight at once (0 = 4, at most 8) */
+    uint32_t blocks_per_lane;    /* 1 or 2 (0 = 2) */
+    uint32_t tile_blocks;        /* 0 = chosen per batch (about two tiles per wave slot) */
+    uint32_t max_batch_requests; /* 0 = no limit */
+    uint64_t max_batch_bytes;    /* 0 = no limit */
+    uint32_t max_queued;         /* waiting requests before EAGAIN (0 = 2^20) */
+    uint32_t reserved;
+} aesgpu_server_config;
+
+/* A finished request.  d_out points into the server's arena and stays valid
+ * until aesgpu_server_release().  Times are seconds on the server clock
+ * (aesgpu_server_now()). */
+typedef struct {
+    uint64_t req_id;
+    int32_t status;     /* AESGPU_OK or the error that failed its batch */
+    uint32_t reserved;
+    void *d_out;
+    uint64_t n_bytes;
+    double t_arrival;   /* as passed to submit */
+    double t_launch;    /* its batch was enqueued */
+    double t_done;      /* its batch was seen complete */
+} aesgpu_done;
+
+/* One request of a replayed arrival trace (t_arrival relative to t_start). */
+typedef struct {
+    uint64_t req_id;    /* 0 .. n-1, each once */
+    double t_arrival;
+    const void *d_in;
+    uint64_t n_bytes;
+    uint32_t key_id;
+    uint32_t dir;       /* AESGPU_DIR_ENCRYPT or AESGPU_DIR_DECRYPT */
+} aesgpu_request;
+
+typedef struct {
+    uint64_t batches;
+    uint64_t requests_submitted;
+    uint64_t requests_done;
+    uint64_t bytes_done;
+    uint64_t max_batch_requests;
+    uint64_t queued;             /* waiting for admission now */
+    uint64_t arena_used;
+    uint64_t arena_high_water;
+} aesgpu_server_stats;
+
+/*
+ * Starts a server on ctx's device: expands the n_keys pool keys (raw bytes at
+ * a 32-byte stride in host memory `keys`, sizes in key_bits) and keeps their
+ * encryption and decryption schedules resident on the device, allocates the
+ * output arena and the streams, and starts the dispatcher thread.  Requests
+ * are ECB (the paper's section 3 parallel mode) in either direction.  Each
+ * dispatch launches all admitted requests as one batched run (the persistent
+ * launch of aesgpu_batch_run, with resident schedules instead of device key
+ * expansion).  Errors: EINVAL, EKEYLEN, ENOMEM, EHIP.
+ */
+int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *key_bits,
+                         size_t n_keys, const aesgpu_server_config *cfg, aesgpu_server **out);
+
+/* Seconds since the server started (steady clock). */
+double aesgpu_server_now(const aesgpu_server *server);
+
+/*
+ * Queues one request: ECB encrypt (dir 0) or decrypt (dir 1) of n_bytes (a
+ * multiple of 16, at most the arena size) at device pointer d_in (16-byte
+ * aligned, must stay valid until the request completes) with pool key key_id.
+ * Requests are admitted first come first served as arena space frees up.
+ * Returns EAGAIN when max_queued requests are already waiting; EINVAL /
+ * EALIGN for bad arguments; a zero-length request completes at once.
+ * Thread-safe.
+ */
+int aesgpu_server_submit(aesgpu_server *server, uint64_t req_id, int dir, uint32_t key_id,
+                         const void *d_in, size_t n_bytes, double t_arrival);
+
+/* Moves up to cap finished requests into out[]; *n_done receives the count. */
+int aesgpu_server_poll(aesgpu_server *server, aesgpu_done *out, size_t cap, size_t *n_done);
+
+/* Returns a finished request's output range (d_out, n_bytes) to the arena. */
+int aesgpu_server_release(aesgpu_server *server, const void *d_out, size_t n_bytes);
+
+int aesgpu_server_get_stats(aesgpu_server *server, aesgpu_server_stats *out);
+
+/*
+ * Load generator: submits reqs[i] at time t_start + reqs[i].t_arrival on the
+ * server clock (in order, retrying while the queue is full), polls and
+ * releases outputs as they finish, and returns when all n are done, with
+ * done[req_id] filled.  Runs in the calling thread.  Errors: EINVAL, or the
+ * first failed request's status.
+ */
+int aesgpu_server_replay(aesgpu_server *server, const aesgpu_request *reqs, size_t n,
+                         double t_start, aesgpu_done *done);
+
+/* Stops the dispatcher after the batches in flight finish and frees the
+ * server (arena, schedules, streams).  NULL is ignored. */
+void aesgpu_server_destroy(aesgpu_server *server);
 
 /* Human-readable name of a status code (static string, never NULL). */
 const char *aesgpu_strerror(int status);

@@ -69,7 +69,34 @@ class aesgpu_batch_stats(ctypes.Structure):
                 ("launches", ctypes.c_uint32)]
 
 
+class aesgpu_server_config(ctypes.Structure):
+    _fields_ = [("arena_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_uint32),
+                ("blocks_per_lane", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
+                ("max_batch_requests", ctypes.c_uint32), ("max_batch_bytes", ctypes.c_uint64),
+                ("max_queued", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class aesgpu_done(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_uint32), ("d_out", ctypes.c_void_p),
+                ("n_bytes", ctypes.c_uint64), ("t_arrival", ctypes.c_double),
+                ("t_launch", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class aesgpu_request(ctypes.Structure):
+    _fields_ = [("req_id", ctypes.c_uint64), ("t_arrival", ctypes.c_double),
+                ("d_in", ctypes.c_void_p), ("n_bytes", ctypes.c_uint64),
+                ("key_id", ctypes.c_uint32), ("dir", ctypes.c_uint32)]
+
+
+class aesgpu_server_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("batches", "requests_submitted", "requests_done", "bytes_done",
+                 "max_batch_requests", "queued", "arena_used", "arena_high_water")]
+
+
 assert ctypes.sizeof(aesgpu_msg) == 48
+assert ctypes.sizeof(aesgpu_done) == 56 and ctypes.sizeof(aesgpu_request) == 40
 
 
 def _load() -> ctypes.CDLL:
@@ -95,6 +122,22 @@ def _load() -> ctypes.CDLL:
         "aesgpu_batch_run": ([vp, vp, sz, vp, sz, vp, sz, vp], ci),
         "aesgpu_batch_info": ([vp, ctypes.POINTER(aesgpu_batch_stats)], ci),
         "aesgpu_batch_free": ([vp], None),
+        "aesgpu_arena_create": ([ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(vp)], ci),
+        "aesgpu_arena_alloc": ([vp, ctypes.c_uint64, ctypes.POINTER(ctypes.c_uint64)], ci),
+        "aesgpu_arena_release": ([vp, ctypes.c_uint64, ctypes.c_uint64], ci),
+        "aesgpu_arena_query": ([vp] + [ctypes.POINTER(ctypes.c_uint64)] * 3, ci),
+        "aesgpu_arena_destroy": ([vp], None),
+        "aesgpu_server_create": ([vp, u8p, ctypes.POINTER(ctypes.c_uint16), sz,
+                                  ctypes.POINTER(aesgpu_server_config), ctypes.POINTER(vp)], ci),
+        "aesgpu_server_now": ([vp], ctypes.c_double),
+        "aesgpu_server_submit": ([vp, ctypes.c_uint64, ci, ctypes.c_uint32, vp, sz,
+                                  ctypes.c_double], ci),
+        "aesgpu_server_poll": ([vp, ctypes.POINTER(aesgpu_done), sz, ctypes.POINTER(sz)], ci),
+        "aesgpu_server_release": ([vp, vp, sz], ci),
+        "aesgpu_server_get_stats": ([vp, ctypes.POINTER(aesgpu_server_stats)], ci),
+        "aesgpu_server_replay": ([vp, ctypes.POINTER(aesgpu_request), sz, ctypes.c_double,
+                                  ctypes.POINTER(aesgpu_done)], ci),
+        "aesgpu_server_destroy": ([vp], None),
         "aesgpu_strerror": ([ci], ctypes.c_char_p),
         "aesgpu_ctx_num_cus": ([vp], ci),
     }
@@ -288,3 +331,121 @@ def aesgpu_batch_info(plan) -> aesgpu_batch_stats:
 
 def aesgpu_batch_free(plan) -> None:
     _lib.aesgpu_batch_free(plan)
+
+
+# ---- range allocator ---------------------------------------------------------------
+
+def aesgpu_arena_create(capacity: int, granule: int = 256):
+    h = ctypes.c_void_p()
+    _check(_lib.aesgpu_arena_create(capacity, granule, ctypes.byref(h)), "aesgpu_arena_create")
+    return h
+
+
+def aesgpu_arena_alloc(arena, n_bytes: int):
+    """Offset of the new range, or None when nothing fits right now (EAGAIN)."""
+    off = ctypes.c_uint64()
+    st = _lib.aesgpu_arena_alloc(arena, n_bytes, ctypes.byref(off))
+    if st == AESGPU_EAGAIN:
+        return None
+    _check(st, "aesgpu_arena_alloc")
+    return off.value
+
+
+def aesgpu_arena_release(arena, offset: int, n_bytes: int, check: bool = True) -> int:
+    st = _lib.aesgpu_arena_release(arena, offset, n_bytes)
+    return _check(st, "aesgpu_arena_release") if check else st
+
+
+def aesgpu_arena_query(arena) -> tuple[int, int, int]:
+    """(used, largest free range, high-water mark) in bytes."""
+    u, f, h = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
+    _check(_lib.aesgpu_arena_query(arena, ctypes.byref(u), ctypes.byref(f), ctypes.byref(h)),
+           "aesgpu_arena_query")
+    return u.value, f.value, h.value
+
+
+def aesgpu_arena_destroy(arena) -> None:
+    _lib.aesgpu_arena_destroy(arena)
+
+
+# ---- serving ------------------------------------------------------------------------
+
+def aesgpu_server_create(ctx, keys, key_bits, arena_bytes: int, n_streams: int = 0,
+                         blocks_per_lane: int = 0, tile_blocks: int = 0,
+                         max_batch_requests: int = 0, max_batch_bytes: int = 0,
+                         max_queued: int = 0):
+    """keys: (n, 32) uint8 host array (key bytes first); key_bits: n sizes."""
+    import numpy as np
+    k = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
+    bits = np.ascontiguousarray(key_bits, dtype=np.uint16).reshape(-1)
+    assert bits.size == k.shape[0]
+    cfg = aesgpu_server_config(arena_bytes, n_streams, blocks_per_lane, tile_blocks,
+                               max_batch_requests, max_batch_bytes, max_queued, 0)
+    h = ctypes.c_void_p()
+    _check(_lib.aesgpu_server_create(ctx, k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                     bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                     bits.size, ctypes.byref(cfg), ctypes.byref(h)),
+           "aesgpu_server_create")
+    return h
+
+
+def aesgpu_server_now(server) -> float:
+    return float(_lib.aesgpu_server_now(server))
+
+
+def aesgpu_server_submit(server, req_id: int, dir: int, key_id: int, d_in, n_bytes=None,
+                         t_arrival: float | None = None, check: bool = True) -> int:
+    if n_bytes is None:
+        n_bytes = _nbytes(d_in)
+    if t_arrival is None:
+        t_arrival = aesgpu_server_now(server)
+    st = _lib.aesgpu_server_submit(server, req_id, dir, key_id, _ptr(d_in), n_bytes, t_arrival)
+    return _check(st, "aesgpu_server_submit") if check else st
+
+
+def aesgpu_server_poll(server, cap: int = 1024) -> list:
+    buf = (aesgpu_done * cap)()
+    n = ctypes.c_size_t()
+    _check(_lib.aesgpu_server_poll(server, buf, cap, ctypes.byref(n)), "aesgpu_server_poll")
+    return [buf[i] for i in range(n.value)]
+
+
+def aesgpu_server_release(server, d_out, n_bytes: int) -> int:
+    return _check(_lib.aesgpu_server_release(server, d_out, n_bytes), "aesgpu_server_release")
+
+
+def aesgpu_server_get_stats(server) -> aesgpu_server_stats:
+    st = aesgpu_server_stats()
+    _check(_lib.aesgpu_server_get_stats(server, ctypes.byref(st)), "aesgpu_server_get_stats")
+    return st
+
+
+def aesgpu_server_replay(server, reqs, t_start: float):
+    """reqs: ctypes array of aesgpu_request; returns a ctypes array of
+    aesgpu_done indexed by req_id."""
+    n = len(reqs)
+    done = (aesgpu_done * n)()
+    _check(_lib.aesgpu_server_replay(server, reqs, n, t_start, done), "aesgpu_server_replay")
+    return done
+
+
+def make_requests(t_arrival, d_in, n_bytes, key_id, dir):
+    """Array of ``aesgpu_request`` (req_id = position) from per-request
+    sequences; ``d_in`` holds device addresses."""
+    import numpy as np
+    n = len(n_bytes)
+    arr = (aesgpu_request * n)()
+    view = np.frombuffer(arr, dtype=np.dtype(
+        [("req_id", "<u8"), ("t_arrival", "<f8"), ("d_in", "<u8"), ("n_bytes", "<u8"),
+         ("key_id", "<u4"), ("dir", "<u4")]), count=n)
+    view["req_id"] = np.arange(n)
+    view["t_arrival"] = t_arrival
+    view["d_in"] = d_in
+    view["n_bytes"] = n_bytes
+    view["key_id"] = key_id
+    view["dir"] = dir
+    return arr
+
+
+def aesgpu_server_destroy(server) -> None:
+    _lib.aesgpu_server_destroy(server)

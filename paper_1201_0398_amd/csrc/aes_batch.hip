@@ -32,33 +32,15 @@ namespace {
 
 using namespace dev;
 
-struct alignas(16) DevMsg {
-    uint64_t in_off;
-    uint64_t out_off;
-    uint64_t n_full;    // whole blocks
-    uint32_t tail;      // bytes of a final partial block (CTR only)
-    uint32_t key_slot;
-    uint32_t nr;
-    uint32_t mode;      // AESGPU_MODE_ECB / AESGPU_MODE_CTR
-    uint32_t nonce[3];
-    uint32_t ctr0;
-    uint32_t pad[2];
-};
-static_assert(sizeof(DevMsg) == 64, "descriptor layout");
-
-struct alignas(16) Tile {
-    uint32_t msg;
-    uint32_t n_blocks;      // blocks in this tile (the partial CTR block counts)
-    uint64_t first_block;   // first block of the tile within its message
-};
-static_assert(sizeof(Tile) == 16, "tile layout");
-
 struct BatchParams {
     const DevMsg *msgs;
-    const Tile *tiles;
-    uint32_t n_tiles;
-    uint32_t *counter;
-    const uint8_t *keys;   // raw key bytes, 32-byte stride
+    const Tile *tiles[2];   // forward-set and inverse-set queues
+    uint32_t n_tiles[2];
+    uint32_t *counters;     // dynamic pulls of each queue, then one flag word per workgroup
+    uint32_t n_wg_forward_first;  // workgroups that start on the forward queue
+    uint32_t n_static[2];   // tiles handed out statically (one per wave of the starting WGs)
+    const uint8_t *keys;    // raw key bytes, 32-byte stride (device expansion)
+    const uint32_t *sched;  // or resident schedules, kSchedWords per key slot
     const uint8_t *in;
     uint8_t *out;
     const uint32_t *tables;
@@ -139,19 +121,50 @@ __device__ __forceinline__ uint32_t decrypt_keys(const uint32_t *lds, const Base
     return acc;
 }
 
-// Round key r as four SGPRs, read from the schedule register.
-__device__ __forceinline__ void round_key(uint32_t kreg, int r, uint32_t (&k)[4]) {
+// Round key r (wave-uniform, possibly a run-time value) as four SGPRs, read
+// from the schedule register.
+__device__ __forceinline__ void round_key(uint32_t kreg, uint32_t r, uint32_t (&k)[4]) {
 #pragma unroll
-    for (int c = 0; c < 4; ++c) k[c] = __builtin_amdgcn_readlane(kreg, 4 * r + c);
+    for (int c = 0; c < 4; ++c) k[c] = __builtin_amdgcn_readlane(kreg, int(4 * r + c));
 }
 
-// One tile: NR rounds on BPL blocks per lane per step.
-template <bool kInv, int NR, int BPL>
+// Device key expansion for the message's key size.
+template <bool kInv>
+__device__ __forceinline__ uint32_t schedule_of(const uint32_t *lds, const Bases &b,
+                                                const uint32_t *key, uint32_t nr) {
+    uint32_t kreg;
+    if (nr == 10) {
+        kreg = expand_key<kInv, 10>(lds, key);
+        if constexpr (kInv) kreg = decrypt_keys<10>(lds, b, kreg);
+    } else if (nr == 12) {
+        kreg = expand_key<kInv, 12>(lds, key);
+        if constexpr (kInv) kreg = decrypt_keys<12>(lds, b, kreg);
+    } else {
+        kreg = expand_key<kInv, 14>(lds, key);
+        if constexpr (kInv) kreg = decrypt_keys<14>(lds, b, kreg);
+    }
+    return kreg;
+}
+
+// One tile: nr rounds on BPL blocks per lane per step.  The round loop is not
+// unrolled and takes nr at run time: one short loop body serves all key
+// sizes, so the code a workgroup runs fits the instruction cache even when
+// each CU executes it only once (small batches).
+template <bool kInv, int BPL>
 __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, const BatchParams &p,
                                          const DevMsg &m, const Tile &tile) {
-    const uint32_t *key = reinterpret_cast<const uint32_t *>(p.keys + 32ull * m.key_slot);
-    uint32_t kreg = expand_key<kInv, NR>(lds, key);
-    if constexpr (kInv) kreg = decrypt_keys<NR>(lds, b, kreg);
+    const uint32_t nr = m.nr;
+    uint32_t kreg;
+    if (p.sched) {
+        // Resident schedule: lane i loads word i (encryption words first,
+        // then the equivalent-inverse-cipher words).
+        const uint32_t lane = threadIdx.x & 63u;
+        const uint32_t *w = p.sched + uint64_t(m.key_slot) * kSchedWords + (kInv ? 64u : 0u);
+        kreg = lane < 4u * (nr + 1) ? w[lane] : 0u;
+    } else {
+        const uint32_t *key = reinterpret_cast<const uint32_t *>(p.keys + 32ull * m.key_slot);
+        kreg = schedule_of<kInv>(lds, b, key, nr);
+    }
 
     const bool ctr = !kInv && m.mode == AESGPU_MODE_CTR;
     CtrConsts cc{};
@@ -181,9 +194,18 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     uint4 *out = reinterpret_cast<uint4 *>(p.out + m.out_off);
     const uint64_t end = tile.first_block + tile.n_blocks;
     constexpr uint32_t kStep = 64u * BPL;
+    const uint64_t lim = end < m.n_full ? end : m.n_full;  // whole blocks of this tile
+    // The next step's blocks are loaded while the current step is computed.
+    uint4 next[BPL];
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+        const uint64_t idx = tile.first_block + uint64_t(j) * 64u + lane;
+        next[j] = make_uint4(0, 0, 0, 0);
+        if (idx < lim) next[j] = in[idx];
+    }
     for (uint64_t base = tile.first_block; base < end; base += kStep) {
         // Keep the round-key reads inside the loop: hoisting all of them would
-        // need 4 * (NR + 1) SGPRs at once.
+        // need 4 * (nr + 1) SGPRs at once.
         asm volatile("" : "+v"(kreg));
         uint32_t s[BPL][4];
         uint4 d[BPL];
@@ -191,9 +213,14 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
         round_key(kreg, 0, rk);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
+            d[j] = next[j];
+            const uint64_t nidx = base + kStep + uint64_t(j) * 64u + lane;
+            next[j] = make_uint4(0, 0, 0, 0);
+            if (nidx < lim) next[j] = in[nidx];
+        }
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) {
             const uint64_t idx = base + uint64_t(j) * 64u + lane;
-            d[j] = make_uint4(0, 0, 0, 0);
-            if (idx < end && idx < m.n_full) d[j] = in[idx];
             if (ctr) {
                 const uint32_t w3 = __builtin_amdgcn_perm(m.ctr0 + uint32_t(idx),
                                                           m.ctr0 + uint32_t(idx), 0x00010203u) ^
@@ -214,13 +241,13 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
 #pragma unroll
             for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], rk);
         }
-#pragma unroll
-        for (int r = 2; r < NR; ++r) {
+#pragma unroll 1
+        for (uint32_t r = 2; r < nr; ++r) {
             round_key(kreg, r, rk);
 #pragma unroll
             for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], rk);
         }
-        round_key(kreg, NR, rk);
+        round_key(kreg, nr, rk);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             if constexpr (kInv)
@@ -252,26 +279,74 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     }
 }
 
+// Runs tiles of one table set's queue until it is empty.  A wave first runs
+// its static tile (`first`, or kNone) and then pulls tiles n_static,
+// n_static + 1, ... from the queue's atomic counter, so a launch does no
+// atomic at all when every tile has a wave of its own.
+constexpr uint32_t kNone = 0xFFFFFFFFu;
+
 template <bool kInv, int BPL>
-__global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
-    __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords];
-    stage_tables<kInv>(lds, p.tables);
-    const Bases b = lane_bases();
+__device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
+                                            const BatchParams &p, uint32_t first) {
+    constexpr int set = kInv ? 1 : 0;
     const DevMsg *__restrict__ msgs = p.msgs;
-    const Tile *__restrict__ tiles = p.tiles;
+    const Tile *__restrict__ tiles = p.tiles[set];
+    uint32_t t = first;
     for (;;) {
-        uint32_t t = 0;
-        if ((threadIdx.x & 63u) == 0) t = atomicAdd(p.counter, 1u);
-        t = __builtin_amdgcn_readfirstlane(t);
-        if (t >= p.n_tiles) break;
+        if (t == kNone) {
+            if (p.n_static[set] >= p.n_tiles[set]) break;  // no dynamic tiles at all
+            uint32_t c = 0;
+            if ((threadIdx.x & 63u) == 0) c = atomicAdd(&p.counters[set], 1u);
+            t = p.n_static[set] + __builtin_amdgcn_readfirstlane(c);
+        }
+        if (t >= p.n_tiles[set]) break;
         const Tile tile = tiles[t];
         const DevMsg m = msgs[tile.msg];
-        if (m.nr == 10)
-            run_tile<kInv, 10, BPL>(lds, b, p, m, tile);
-        else if (m.nr == 12)
-            run_tile<kInv, 12, BPL>(lds, b, p, m, tile);
-        else
-            run_tile<kInv, 14, BPL>(lds, b, p, m, tile);
+        run_tile<kInv, BPL>(lds, b, p, m, tile);
+        t = kNone;
+    }
+}
+
+// One launch for both table sets: workgroups below n_wg_forward_first start
+// on the forward queue, the others on the inverse queue; wave w of the i-th
+// workgroup of a set owns static tile 16 i + w of that set.  A workgroup
+// whose queue runs dry waits until all its waves are done with the LDS
+// tables, then stages the other set and helps drain the other queue (if
+// tiles are left there).
+template <int BPL>
+__global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
+    __shared__ uint32_t lds[kFwdWords + kInvSWords];
+    const Bases b = lane_bases();
+    const uint32_t first = blockIdx.x < p.n_wg_forward_first ? 0u : 1u;
+    const uint32_t wg_in_set = first ? blockIdx.x - p.n_wg_forward_first : blockIdx.x;
+    const uint32_t my_static = wg_in_set * (kWG / 64) + (threadIdx.x >> 6);
+    for (uint32_t pass = 0; pass < 2; ++pass) {
+        const uint32_t set = pass ^ first;
+        // Stage the set only if this workgroup has work in it: a static tile
+        // (first pass) or dynamic tiles still queued.  One thread decides and
+        // publishes the decision in this workgroup's flag word (the LDS is
+        // full), so that every wave takes the same branch.
+        uint32_t *flag = p.counters + 2 + blockIdx.x;
+        __syncthreads();  // all waves are past the previous queue
+        if (threadIdx.x == 0) {
+            const uint32_t pulled =
+                __hip_atomic_load(&p.counters[set], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            const bool has_static = pass == 0 && wg_in_set * (kWG / 64) < p.n_tiles[set];
+            const bool has_dynamic = p.n_static[set] < p.n_tiles[set] &&
+                                     pulled < p.n_tiles[set] - p.n_static[set];
+            __hip_atomic_store(flag, (has_static || has_dynamic) ? 1u : 0u, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+        __syncthreads();
+        if (!__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) continue;
+        const uint32_t start = (pass == 0 && my_static < p.n_tiles[set]) ? my_static : kNone;
+        if (set == 0) {
+            stage_tables<false>(lds, p.tables);
+            drain_queue<false, BPL>(lds, b, p, start);
+        } else {
+            stage_tables<true>(lds, p.tables);
+            drain_queue<true, BPL>(lds, b, p, start);
+        }
     }
 }
 
@@ -279,110 +354,46 @@ __global__ void reset_counters(uint32_t *c, uint32_t n) {
     if (threadIdx.x < n) c[threadIdx.x] = 0;
 }
 
-constexpr uint32_t kDefaultBpl = 4;
-constexpr uint32_t kDefaultTileBlocks = 2048;
-
-}  // namespace
-}  // namespace aesgpu
-
-using namespace aesgpu;
-
-struct aesgpu_batch {
-    aesgpu_ctx *ctx = nullptr;
-    uint32_t bpl = kDefaultBpl;
-    uint32_t tile_blocks = kDefaultTileBlocks;
-    bool use_graph = true;
-    size_t n_msgs = 0;
-    size_t n_tiles[2] = {0, 0};    // forward, inverse
-    uint64_t total_bytes = 0;
-    uint64_t in_end = 0, out_end = 0;
-    uint32_t max_slot = 0;
-    void *d_mem = nullptr;         // messages | forward tiles | inverse tiles | counters
-    DevMsg *d_msgs = nullptr;
-    Tile *d_tiles[2] = {nullptr, nullptr};
-    uint32_t *d_counters = nullptr;
-    hipStream_t cap_stream = nullptr;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
-    const void *cap_keys = nullptr, *cap_in = nullptr;
-    void *cap_out = nullptr;
-};
-
-namespace {
-
-uint32_t le32(const uint8_t *p) {
-    return uint32_t(p[0]) | (uint32_t(p[1]) << 8) | (uint32_t(p[2]) << 16) | (uint32_t(p[3]) << 24);
-}
-
-class DeviceGuard {
-  public:
-    explicit DeviceGuard(int device) {
-        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-        ok_ = prev_ == device || hipSetDevice(device) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev_ >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
-    }
-    bool ok() const { return ok_; }
-
-  private:
-    int prev_ = -1;
-    bool ok_ = false;
-};
-
-void release_graph(aesgpu_batch *b) {
-    if (b->exec) (void)hipGraphExecDestroy(b->exec);
-    if (b->graph) (void)hipGraphDestroy(b->graph);
-    b->exec = nullptr;
-    b->graph = nullptr;
-}
-
 template <int BPL>
-int enqueue_t(aesgpu_batch *b, const uint8_t *keys, const void *in, void *out, hipStream_t s) {
-    hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, b->d_counters, 2u);
-    for (int set = 0; set < 2; ++set) {
-        if (!b->n_tiles[set]) continue;
-        BatchParams p{b->d_msgs, b->d_tiles[set], uint32_t(b->n_tiles[set]), b->d_counters + set,
-                      keys, static_cast<const uint8_t *>(in), static_cast<uint8_t *>(out),
-                      b->ctx->d_tables};
-        const uint32_t grid = uint32_t(std::min<size_t>(b->ctx->n_cu, b->n_tiles[set]));
-        if (set == 0)
-            hipLaunchKernelGGL((batch_kernel<false, BPL>), dim3(grid), dim3(kWG), 0, s, p);
-        else
-            hipLaunchKernelGGL((batch_kernel<true, BPL>), dim3(grid), dim3(kWG), 0, s, p);
+int enqueue_t(const BatchLaunch &L, hipStream_t s) {
+    const uint32_t total = L.n_tiles[0] + L.n_tiles[1];
+    if (!total) return AESGPU_OK;
+    if (L.reset_counters)
+        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, L.counters, 2u);
+    // About one tile per wave for small batches, one workgroup per CU at most.
+    constexpr uint32_t kWaves = kWG / 64;
+    uint32_t grid = (total + kWaves - 1) / kWaves;
+    if (grid > uint32_t(L.n_cu)) grid = uint32_t(L.n_cu);
+    if (grid > 1024) grid = 1024;  // one flag word per workgroup in the counter area
+    if (grid < 2 && L.n_tiles[0] && L.n_tiles[1]) grid = 2;
+    // Split the workgroups between the queues in proportion to their blocks.
+    uint32_t fwd = 0;
+    if (!L.n_tiles[1]) {
+        fwd = grid;
+    } else if (L.n_tiles[0]) {
+        const double share = double(L.blocks[0]) / double(L.blocks[0] + L.blocks[1]);
+        fwd = uint32_t(share * grid + 0.5);
+        fwd = fwd < 1 ? 1 : (fwd > grid - 1 ? grid - 1 : fwd);
     }
+    BatchParams p{L.msgs,     {L.tiles[0], L.tiles[1]}, {L.n_tiles[0], L.n_tiles[1]},
+                  L.counters, fwd,  {fwd * kWaves, (grid - fwd) * kWaves},
+                  L.keys,     L.sched, L.in, L.out, L.tables};
+    hipLaunchKernelGGL((batch_kernel<BPL>), dim3(grid), dim3(kWG), 0, s, p);
     return hipGetLastError() == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
 }
 
-int enqueue(aesgpu_batch *b, const uint8_t *keys, const void *in, void *out, hipStream_t s) {
-    return b->bpl == 2 ? enqueue_t<2>(b, keys, in, out, s) : enqueue_t<4>(b, keys, in, out, s);
-}
-
 }  // namespace
 
-extern "C" {
+int enqueue_batch(const BatchLaunch &L, hipStream_t s) {
+    return L.bpl == 1 ? enqueue_t<1>(L, s) : enqueue_t<2>(L, s);
+}
 
-int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
-                      const aesgpu_batch_config *cfg, aesgpu_batch **out) {
-    if (!out) return AESGPU_EINVAL;
-    *out = nullptr;
-    if (!ctx || (m > 0 && !msgs)) return AESGPU_EINVAL;
-    if (m > 0xFFFFFFFFull) return AESGPU_EINVAL;
-    uint32_t bpl = kDefaultBpl, tile_blocks = kDefaultTileBlocks;
-    bool use_graph = true;
-    if (cfg) {
-        if (cfg->blocks_per_lane) bpl = cfg->blocks_per_lane;
-        if (cfg->tile_blocks) tile_blocks = cfg->tile_blocks;
-        use_graph = !(cfg->flags & AESGPU_BATCH_NO_GRAPH);
-    }
-    if (bpl != 2 && bpl != 4) return AESGPU_EINVAL;
-    if (tile_blocks % (64u * bpl) != 0 || tile_blocks > (1u << 24)) return AESGPU_EINVAL;
-
-    std::vector<DevMsg> dm(m);
-    std::vector<Tile> tiles[2];
-    uint64_t total = 0, in_end = 0, out_end = 0;
-    uint32_t max_slot = 0;
+int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vector<DevMsg> &dm,
+                std::vector<Tile> (&tiles)[2], BatchTotals &tot) {
+    dm.resize(m);
+    tiles[0].clear();
+    tiles[1].clear();
+    tot = BatchTotals{};
     for (size_t i = 0; i < m; ++i) {
         const aesgpu_msg &x = msgs[i];
         if (x.key_bits != 128 && x.key_bits != 192 && x.key_bits != 256) return AESGPU_EKEYLEN;
@@ -407,13 +418,14 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
         d.mode = x.mode;
         for (int c = 0; c < 3; ++c) d.nonce[c] = le32(x.nonce + 4 * c);
         d.ctr0 = x.ctr0;
-        total += x.n_bytes;
+        tot.total += x.n_bytes;
         if (x.n_bytes) {
-            in_end = std::max(in_end, x.in_off + x.n_bytes);
-            out_end = std::max(out_end, x.out_off + x.n_bytes);
-            max_slot = std::max(max_slot, x.key_slot);
+            tot.in_end = std::max(tot.in_end, x.in_off + x.n_bytes);
+            tot.out_end = std::max(tot.out_end, x.out_off + x.n_bytes);
+            tot.max_slot = std::max(tot.max_slot, x.key_slot);
         }
         const int set = (x.mode == AESGPU_MODE_ECB && x.dir == AESGPU_DIR_DECRYPT) ? 1 : 0;
+        tot.blocks[set] += n_blocks;
         for (uint64_t f = 0; f < n_blocks; f += tile_blocks) {
             const uint64_t n = std::min<uint64_t>(tile_blocks, n_blocks - f);
             tiles[set].push_back(Tile{uint32_t(i), uint32_t(n), f});
@@ -422,6 +434,93 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     for (auto &t : tiles)
         std::stable_sort(t.begin(), t.end(),
                          [](const Tile &a, const Tile &b) { return a.n_blocks > b.n_blocks; });
+    return AESGPU_OK;
+}
+
+}  // namespace aesgpu
+
+using namespace aesgpu;
+
+namespace {
+constexpr uint32_t kDefaultBpl = 2;
+constexpr uint32_t kDefaultTileBlocks = 8192;
+}  // namespace
+
+struct aesgpu_batch {
+    aesgpu_ctx *ctx = nullptr;
+    uint32_t bpl = kDefaultBpl;
+    uint32_t tile_blocks = kDefaultTileBlocks;
+    bool use_graph = true;
+    size_t n_msgs = 0;
+    size_t n_tiles[2] = {0, 0};    // forward, inverse
+    BatchTotals tot;
+    void *d_mem = nullptr;         // messages | forward tiles | inverse tiles | counters
+    DevMsg *d_msgs = nullptr;
+    Tile *d_tiles[2] = {nullptr, nullptr};
+    uint32_t *d_counters = nullptr;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *cap_keys = nullptr, *cap_in = nullptr;
+    void *cap_out = nullptr;
+};
+
+namespace {
+
+void release_graph(aesgpu_batch *b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+int enqueue(aesgpu_batch *b, const uint8_t *keys, const void *in, void *out, hipStream_t s) {
+    BatchLaunch L{};
+    L.msgs = b->d_msgs;
+    L.tiles[0] = b->d_tiles[0];
+    L.tiles[1] = b->d_tiles[1];
+    L.n_tiles[0] = uint32_t(b->n_tiles[0]);
+    L.n_tiles[1] = uint32_t(b->n_tiles[1]);
+    L.counters = b->d_counters;
+    L.keys = keys;
+    L.sched = nullptr;
+    L.in = static_cast<const uint8_t *>(in);
+    L.out = static_cast<uint8_t *>(out);
+    L.tables = b->ctx->d_tables;
+    L.n_cu = b->ctx->n_cu;
+    L.bpl = b->bpl;
+    L.blocks[0] = b->tot.blocks[0];
+    L.blocks[1] = b->tot.blocks[1];
+    L.reset_counters = true;
+    return enqueue_batch(L, s);
+}
+
+}  // namespace
+
+extern "C" {
+
+int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
+                      const aesgpu_batch_config *cfg, aesgpu_batch **out) {
+    if (!out) return AESGPU_EINVAL;
+    *out = nullptr;
+    if (!ctx || (m > 0 && !msgs)) return AESGPU_EINVAL;
+    if (m > 0xFFFFFFFFull) return AESGPU_EINVAL;
+    uint32_t bpl = kDefaultBpl, tile_blocks = kDefaultTileBlocks;
+    bool use_graph = true;
+    if (cfg) {
+        if (cfg->blocks_per_lane) bpl = cfg->blocks_per_lane;
+        if (cfg->tile_blocks) tile_blocks = cfg->tile_blocks;
+        use_graph = !(cfg->flags & AESGPU_BATCH_NO_GRAPH);
+    }
+    if (bpl != 1 && bpl != 2) return AESGPU_EINVAL;
+    if (tile_blocks % (64u * bpl) != 0 || tile_blocks > (1u << 24)) return AESGPU_EINVAL;
+
+    std::vector<DevMsg> dm;
+    std::vector<Tile> tiles[2];
+    BatchTotals tot;
+    const int st = build_tiles(msgs, m, tile_blocks, dm, tiles, tot);
+    if (st != AESGPU_OK) return st;
+    if (tiles[0].size() > 0xFFFFFFFFull || tiles[1].size() > 0xFFFFFFFFull) return AESGPU_EINVAL;
 
     aesgpu_batch *b = new (std::nothrow) aesgpu_batch;
     if (!b) return AESGPU_ENOMEM;
@@ -432,10 +531,7 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     b->n_msgs = m;
     b->n_tiles[0] = tiles[0].size();
     b->n_tiles[1] = tiles[1].size();
-    b->total_bytes = total;
-    b->in_end = in_end;
-    b->out_end = out_end;
-    b->max_slot = max_slot;
+    b->tot = tot;
 
     DeviceGuard g(ctx->device);
     if (!g.ok()) {
@@ -444,7 +540,7 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     }
     const size_t msg_bytes = m * sizeof(DevMsg);
     const size_t t0 = tiles[0].size() * sizeof(Tile), t1 = tiles[1].size() * sizeof(Tile);
-    const size_t bytes = msg_bytes + t0 + t1 + 64;
+    const size_t bytes = msg_bytes + t0 + t1 + kCounterBytes;
     if (hipMalloc(&b->d_mem, bytes) != hipSuccess) {
         delete b;
         return AESGPU_ENOMEM;
@@ -475,8 +571,8 @@ int aesgpu_batch_run(aesgpu_batch *b, const uint8_t *d_keys, size_t n_key_slots,
     if ((reinterpret_cast<uintptr_t>(d_keys) | reinterpret_cast<uintptr_t>(d_in) |
          reinterpret_cast<uintptr_t>(d_out)) & 15u)
         return AESGPU_EALIGN;
-    if (uint64_t(b->max_slot) >= n_key_slots) return AESGPU_EINVAL;
-    if (b->in_end > in_bytes || b->out_end > out_bytes) return AESGPU_EINVAL;
+    if (uint64_t(b->tot.max_slot) >= n_key_slots) return AESGPU_EINVAL;
+    if (b->tot.in_end > in_bytes || b->tot.out_end > out_bytes) return AESGPU_EINVAL;
     const uintptr_t i0 = reinterpret_cast<uintptr_t>(d_in), o0 = reinterpret_cast<uintptr_t>(d_out);
     if (i0 != o0 && i0 < o0 + out_bytes && o0 < i0 + in_bytes) return AESGPU_EINVAL;
     DeviceGuard g(b->ctx->device);
@@ -511,12 +607,12 @@ int aesgpu_batch_info(const aesgpu_batch *b, aesgpu_batch_stats *out) {
     out->n_msgs = b->n_msgs;
     out->n_tiles_forward = b->n_tiles[0];
     out->n_tiles_inverse = b->n_tiles[1];
-    out->total_bytes = b->total_bytes;
-    out->in_bytes_needed = b->in_end;
-    out->out_bytes_needed = b->out_end;
+    out->total_bytes = b->tot.total;
+    out->in_bytes_needed = b->tot.in_end;
+    out->out_bytes_needed = b->tot.out_end;
     out->blocks_per_lane = b->bpl;
     out->tile_blocks = b->tile_blocks;
-    out->launches = (b->n_tiles[0] ? 1u : 0u) + (b->n_tiles[1] ? 1u : 0u);
+    out->launches = (b->n_tiles[0] + b->n_tiles[1]) ? 1u : 0u;
     return AESGPU_OK;
 }
 

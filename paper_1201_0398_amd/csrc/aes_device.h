@@ -124,16 +124,34 @@ __device__ __forceinline__ void last_round_inv(const uint32_t *lds, const Bases 
     for (int c = 0; c < 4; ++c) s[c] = o[c];
 }
 
+// Copies the table set into the LDS image.  Loads are issued in groups of
+// eight before their LDS writes, so the staging costs a few L2 round trips
+// instead of one per word, with few registers live.  Needs blockDim.x == kWG.
 template <bool kInv>
 __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ g) {
     const uint32_t *src = g + (kInv ? kTd : kTe);
-    for (uint32_t i = threadIdx.x; i < kFwdWords; i += kWG) {
-        const uint32_t t = ((i >> 14) << 1) | ((i >> 5) & 1u);
-        const uint32_t x = (i >> 6) & 0xFFu;
-        lds[i] = src[t * 256u + x];
+    constexpr int kPer = kFwdWords / kWG;
+    constexpr int kGroup = 8;
+#pragma unroll 1
+    for (int k0 = 0; k0 < kPer; k0 += kGroup) {
+        uint32_t v[kGroup];
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) {
+            const uint32_t i = threadIdx.x + uint32_t(k0 + k) * kWG;
+            const uint32_t t = ((i >> 14) << 1) | ((i >> 5) & 1u);
+            const uint32_t x = (i >> 6) & 0xFFu;
+            v[k] = src[t * 256u + x];
+        }
+#pragma unroll
+        for (int k = 0; k < kGroup; ++k) lds[threadIdx.x + uint32_t(k0 + k) * kWG] = v[k];
     }
-    if (kInv) {
-        for (uint32_t i = threadIdx.x; i < kInvSWords; i += kWG) lds[kFwdWords + i] = g[kInvSS + (i >> 5)];
+    if constexpr (kInv) {
+        constexpr int kPerS = kInvSWords / kWG;
+        uint32_t w[kPerS];
+#pragma unroll
+        for (int k = 0; k < kPerS; ++k) w[k] = g[kInvSS + ((threadIdx.x + uint32_t(k) * kWG) >> 5)];
+#pragma unroll
+        for (int k = 0; k < kPerS; ++k) lds[kFwdWords + threadIdx.x + uint32_t(k) * kWG] = w[k];
     }
     __syncthreads();
 }

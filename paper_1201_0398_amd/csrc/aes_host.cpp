@@ -3,7 +3,6 @@
 #include <hip/hip_runtime.h>
 
 #include <cstring>
-#include <mutex>
 
 #include "aes_internal.h"
 
@@ -100,28 +99,6 @@ int check_buffers(const aesgpu_ctx *ctx, const aesgpu_key *key, const void *in, 
         return AESGPU_EINVAL;
     return AESGPU_OK;
 }
-
-uint32_t le32(const uint8_t *p) {
-    return uint32_t(p[0]) | (uint32_t(p[1]) << 8) | (uint32_t(p[2]) << 16) | (uint32_t(p[3]) << 24);
-}
-
-// Makes `ctx->device` current for the duration of a call.
-class DeviceGuard {
-  public:
-    explicit DeviceGuard(int device) {
-        if (hipGetDevice(&prev_) != hipSuccess) prev_ = -1;
-        ok_ = prev_ == device || hipSetDevice(device) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        int cur = -1;
-        if (prev_ >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev_) (void)hipSetDevice(prev_);
-    }
-    bool ok() const { return ok_; }
-
-  private:
-    int prev_ = -1;
-    bool ok_ = false;
-};
 
 int run(aesgpu_ctx *ctx, const LaunchArgs &a, aesgpu_stream_t stream) {
     DeviceGuard g(ctx->device);

@@ -43,6 +43,19 @@ struct Params {
     RoundKeys rk;
 };
 
+// Blocks base + j * kWG + threadIdx.x (j < BPL) that are below n_full; zero
+// for the others.
+template <int BPL>
+__device__ __forceinline__ void load_tile(uint4 (&v)[BPL], const uint4 *in, uint64_t base,
+                                          uint64_t n_full) {
+#pragma unroll
+    for (int j = 0; j < BPL; ++j) {
+        const uint64_t idx = base + uint64_t(j) * kWG + threadIdx.x;
+        v[j] = make_uint4(0, 0, 0, 0);
+        if (idx < n_full) v[j] = in[idx];
+    }
+}
+
 template <Op OP, int NR, int BPL>
 __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
@@ -52,15 +65,20 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
 
     const uint64_t n_total = p.n_full + (p.tail ? 1 : 0);
     const uint64_t tile = uint64_t(kWG) * BPL;
-    for (uint64_t base = uint64_t(blockIdx.x) * tile; base < n_total;
-         base += uint64_t(gridDim.x) * tile) {
+    const uint64_t stride = uint64_t(gridDim.x) * tile;
+    // The blocks of the next tile are loaded while the current one is
+    // computed, so HBM latency overlaps the rounds even at low occupancy.
+    uint4 next[BPL];
+    load_tile<BPL>(next, p.in, uint64_t(blockIdx.x) * tile, p.n_full);
+    for (uint64_t base = uint64_t(blockIdx.x) * tile; base < n_total; base += stride) {
         uint32_t s[BPL][4];
         uint4 in[BPL];
 #pragma unroll
+        for (int j = 0; j < BPL; ++j) in[j] = next[j];
+        load_tile<BPL>(next, p.in, base + stride, p.n_full);
+#pragma unroll
         for (int j = 0; j < BPL; ++j) {
             const uint64_t idx = base + uint64_t(j) * kWG + threadIdx.x;
-            in[j] = make_uint4(0, 0, 0, 0);
-            if (idx < p.n_full) in[j] = p.in[idx];
             if constexpr (OP == Op::kEcbEnc || OP == Op::kEcbDec || OP == Op::kCbcDec) {
                 s[j][0] = in[j].x ^ p.rk.w[0];
                 s[j][1] = in[j].y ^ p.rk.w[1];

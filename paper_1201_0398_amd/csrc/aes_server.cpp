@@ -1,0 +1,541 @@
+// Continuous-batching AES server.
+//
+// Requests (encrypt or decrypt one device buffer in ECB with a key from a
+// resident pool) enter a FIFO.  A dispatcher thread admits requests in order
+// as long as their output fits in a device arena (first-fit ranges), and
+// whenever one of its streams is idle it launches every admitted request as
+// one batched run (the persistent kernel of the batched path, reading the
+// pool's key schedules that stay resident on the device).  Requests that
+// arrive while earlier batches are still on the GPU are admitted and launched
+// on the next free stream, so batches overlap on the device.  Completion is
+// observed through one event per launch; outputs stay in the arena until the
+// caller releases them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "aes_internal.h"
+
+// ---- first-fit range allocator ---------------------------------------------------
+
+struct aesgpu_arena {
+    uint64_t capacity = 0;
+    uint64_t granule = 256;
+    uint64_t used = 0;
+    uint64_t high_water = 0;
+    std::map<uint64_t, uint64_t> free_ranges;  // offset -> length, non-adjacent
+    std::map<uint64_t, uint64_t> live;         // offset -> length of each allocation
+
+    uint64_t round(uint64_t n) const { return (n + granule - 1) / granule * granule; }
+
+    bool alloc(uint64_t n, uint64_t *off) {
+        const uint64_t need = round(n ? n : 1);
+        for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
+            if (it->second < need) continue;
+            *off = it->first;
+            const uint64_t rest = it->second - need;
+            const uint64_t at = it->first + need;
+            free_ranges.erase(it);
+            if (rest) free_ranges.emplace(at, rest);
+            live.emplace(*off, need);
+            used += need;
+            high_water = std::max(high_water, used);
+            return true;
+        }
+        return false;
+    }
+
+    // Returns false unless [off, off + n) is exactly a live allocation.
+    bool release(uint64_t off, uint64_t n) {
+        const uint64_t len = round(n ? n : 1);
+        auto a = live.find(off);
+        if (a == live.end() || a->second != len) return false;
+        live.erase(a);
+        auto next = free_ranges.lower_bound(off);
+        uint64_t start = off, size = len;
+        if (next != free_ranges.end() && next->first == off + len) {
+            size += next->second;
+            next = free_ranges.erase(next);
+        }
+        if (next != free_ranges.begin()) {
+            auto prev = std::prev(next);
+            if (prev->first + prev->second == off) {
+                start = prev->first;
+                size += prev->second;
+                free_ranges.erase(prev);
+            }
+        }
+        free_ranges.emplace(start, size);
+        used -= len;
+        return true;
+    }
+
+    uint64_t largest_free() const {
+        uint64_t m = 0;
+        for (const auto &r : free_ranges) m = std::max(m, r.second);
+        return m;
+    }
+};
+
+extern "C" {
+
+int aesgpu_arena_create(uint64_t capacity, uint64_t granule, aesgpu_arena **out) {
+    if (!out) return AESGPU_EINVAL;
+    *out = nullptr;
+    if (!granule || (granule & (granule - 1)) || capacity % granule || !capacity)
+        return AESGPU_EINVAL;
+    aesgpu_arena *a = new (std::nothrow) aesgpu_arena;
+    if (!a) return AESGPU_ENOMEM;
+    a->capacity = capacity;
+    a->granule = granule;
+    a->free_ranges.emplace(0, capacity);
+    *out = a;
+    return AESGPU_OK;
+}
+
+int aesgpu_arena_alloc(aesgpu_arena *a, uint64_t n_bytes, uint64_t *offset) {
+    if (!a || !offset) return AESGPU_EINVAL;
+    if (a->round(n_bytes ? n_bytes : 1) > a->capacity) return AESGPU_EINVAL;
+    return a->alloc(n_bytes, offset) ? AESGPU_OK : AESGPU_EAGAIN;
+}
+
+int aesgpu_arena_release(aesgpu_arena *a, uint64_t offset, uint64_t n_bytes) {
+    if (!a) return AESGPU_EINVAL;
+    return a->release(offset, n_bytes) ? AESGPU_OK : AESGPU_EINVAL;
+}
+
+int aesgpu_arena_query(const aesgpu_arena *a, uint64_t *used, uint64_t *largest_free,
+                       uint64_t *high_water) {
+    if (!a) return AESGPU_EINVAL;
+    if (used) *used = a->used;
+    if (largest_free) *largest_free = a->largest_free();
+    if (high_water) *high_water = a->high_water;
+    return AESGPU_OK;
+}
+
+void aesgpu_arena_destroy(aesgpu_arena *a) { delete a; }
+
+}  // extern "C"
+
+// ---- server ------------------------------------------------------------------------
+
+using namespace aesgpu;
+
+namespace {
+
+using Clock = std::chrono::steady_clock;
+
+struct Req {
+    uint64_t id;
+    uint32_t key;
+    uint8_t dir;
+    const void *in;
+    uint64_t n;
+    double t_arrival;
+    uint64_t out_off;
+    double t_launch;
+};
+
+struct Slot {
+    hipStream_t stream = nullptr;
+    hipEvent_t done = nullptr;
+    void *d_buf = nullptr;   // descriptors | tiles | counters
+    size_t d_cap = 0;
+    void *h_buf = nullptr;   // pinned staging of the same layout
+    size_t h_cap = 0;
+    bool busy = false;
+    std::vector<Req> reqs;
+};
+
+}  // namespace
+
+struct aesgpu_server {
+    aesgpu_ctx *ctx = nullptr;
+    aesgpu_server_config cfg{};
+    size_t n_keys = 0;
+    std::vector<uint16_t> key_bits;
+    uint32_t *d_sched = nullptr;
+    uint8_t *d_arena = nullptr;
+    aesgpu_arena arena;
+    Clock::time_point t0;
+
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<Req> waiting;
+    std::deque<aesgpu_done> completed;
+    std::vector<Slot> slots;
+    std::thread worker;
+    std::atomic<bool> stop{false};
+    int fatal = AESGPU_OK;
+
+    aesgpu_server_stats stats{};
+
+    double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
+};
+
+namespace {
+
+bool ensure(void **p, size_t *cap, size_t need, bool pinned) {
+    if (*cap >= need) return true;
+    size_t n = std::max(need, *cap * 2);
+    if (*p) (void)(pinned ? hipHostFree(*p) : hipFree(*p));
+    *p = nullptr;
+    *cap = 0;
+    const hipError_t e = pinned ? hipHostMalloc(p, n, hipHostMallocDefault) : hipMalloc(p, n);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return false;
+    }
+    *cap = n;
+    return true;
+}
+
+// Launches the requests in slot.reqs; returns an AESGPU status.
+int launch_slot(aesgpu_server *s, Slot &slot) {
+    const size_t m = slot.reqs.size();
+    std::vector<aesgpu_msg> msgs(m);
+    for (size_t i = 0; i < m; ++i) {
+        const Req &r = slot.reqs[i];
+        aesgpu_msg &x = msgs[i];
+        std::memset(&x, 0, sizeof(x));
+        x.in_off = reinterpret_cast<uintptr_t>(r.in);   // absolute input address
+        x.out_off = r.out_off;                          // relative to the arena
+        x.n_bytes = r.n;
+        x.key_slot = r.key;
+        x.key_bits = s->key_bits[r.key];
+        x.mode = AESGPU_MODE_ECB;
+        x.dir = r.dir;
+    }
+    uint32_t tile_blocks = s->cfg.tile_blocks;
+    if (!tile_blocks) {
+        // Adaptive: about two tiles per wave slot of this stream's share of
+        // the CUs, so that a small batch is still spread over many waves (a
+        // lone wave on a long tile is latency bound) while batches of the
+        // other streams keep CUs to run on; between one step and 8192 blocks.
+        uint64_t blocks = 0;
+        for (const Req &r : slot.reqs) blocks += r.n / 16;
+        const uint64_t step = 64ull * s->cfg.blocks_per_lane;
+        const uint64_t share = std::max<uint64_t>(1, uint64_t(s->ctx->n_cu) / s->cfg.n_streams);
+        const uint64_t target = 2ull * share * 16;
+        uint64_t tb = (blocks + target - 1) / target;
+        tb = (tb + step - 1) / step * step;
+        tile_blocks = uint32_t(std::min<uint64_t>(std::max<uint64_t>(tb, step), 8192));
+    }
+    std::vector<DevMsg> dm;
+    std::vector<Tile> tiles[2];
+    BatchTotals tot;
+    int st = build_tiles(msgs.data(), m, tile_blocks, dm, tiles, tot);
+    if (st != AESGPU_OK) return st;
+    const size_t mb = m * sizeof(DevMsg), t0 = tiles[0].size() * sizeof(Tile),
+                 t1 = tiles[1].size() * sizeof(Tile);
+    const size_t bytes = mb + t0 + t1 + kCounterBytes;
+    if (!ensure(&slot.h_buf, &slot.h_cap, bytes, true) ||
+        !ensure(&slot.d_buf, &slot.d_cap, bytes, false))
+        return AESGPU_ENOMEM;
+    char *h = static_cast<char *>(slot.h_buf);
+    std::memcpy(h, dm.data(), mb);
+    std::memcpy(h + mb, tiles[0].data(), t0);
+    std::memcpy(h + mb + t0, tiles[1].data(), t1);
+    std::memset(h + mb + t0 + t1, 0, 8);  // the two tile counters start at zero
+    if (hipMemcpyAsync(slot.d_buf, slot.h_buf, mb + t0 + t1 + 8, hipMemcpyHostToDevice,
+                       slot.stream) !=
+        hipSuccess)
+        return AESGPU_EHIP;
+    char *d = static_cast<char *>(slot.d_buf);
+    BatchLaunch L{};
+    L.msgs = reinterpret_cast<const DevMsg *>(d);
+    L.tiles[0] = reinterpret_cast<const Tile *>(d + mb);
+    L.tiles[1] = reinterpret_cast<const Tile *>(d + mb + t0);
+    L.n_tiles[0] = uint32_t(tiles[0].size());
+    L.n_tiles[1] = uint32_t(tiles[1].size());
+    L.counters = reinterpret_cast<uint32_t *>(d + mb + t0 + t1);
+    L.keys = nullptr;
+    L.sched = s->d_sched;
+    L.in = nullptr;
+    L.out = s->d_arena;
+    L.tables = s->ctx->d_tables;
+    L.n_cu = s->ctx->n_cu;
+    L.bpl = s->cfg.blocks_per_lane;
+    L.blocks[0] = tot.blocks[0];
+    L.blocks[1] = tot.blocks[1];
+    L.reset_counters = false;  // zeroed by the copy above
+    st = enqueue_batch(L, slot.stream);
+    if (st != AESGPU_OK) return st;
+    return hipEventRecord(slot.done, slot.stream) == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
+}
+
+void finish_slot(aesgpu_server *s, Slot &slot, int status, double t) {
+    for (const Req &r : slot.reqs) {
+        aesgpu_done d{};
+        d.req_id = r.id;
+        d.status = status;
+        d.d_out = s->d_arena + r.out_off;
+        d.n_bytes = r.n;
+        d.t_arrival = r.t_arrival;
+        d.t_launch = r.t_launch;
+        d.t_done = t;
+        s->completed.push_back(d);
+        s->stats.requests_done++;
+        s->stats.bytes_done += r.n;
+    }
+    slot.reqs.clear();
+    slot.busy = false;
+}
+
+void worker_main(aesgpu_server *s) {
+    if (hipSetDevice(s->ctx->device) != hipSuccess) {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->fatal = AESGPU_EHIP;
+        return;
+    }
+    while (!s->stop.load(std::memory_order_acquire)) {
+        bool in_flight = false;
+        // 1. Completions.
+        for (Slot &slot : s->slots) {
+            if (!slot.busy) continue;
+            const hipError_t q = hipEventQuery(slot.done);
+            if (q == hipErrorNotReady) {
+                in_flight = true;
+                continue;
+            }
+            const double t = s->now();
+            std::lock_guard<std::mutex> g(s->mu);
+            finish_slot(s, slot, q == hipSuccess ? AESGPU_OK : AESGPU_EHIP, t);
+        }
+        // 2. Admission and launch on every idle stream.
+        for (Slot &slot : s->slots) {
+            if (slot.busy) continue;
+            {
+                std::lock_guard<std::mutex> g(s->mu);
+                uint64_t bytes = 0;
+                while (!s->waiting.empty()) {
+                    Req &r = s->waiting.front();
+                    if (s->cfg.max_batch_requests && slot.reqs.size() >= s->cfg.max_batch_requests)
+                        break;
+                    if (s->cfg.max_batch_bytes && !slot.reqs.empty() &&
+                        bytes + r.n > s->cfg.max_batch_bytes)
+                        break;
+                    uint64_t off = 0;
+                    if (!s->arena.alloc(r.n, &off)) break;  // FIFO: wait for memory
+                    r.out_off = off;
+                    bytes += r.n;
+                    slot.reqs.push_back(r);
+                    s->waiting.pop_front();
+                }
+            }
+            if (slot.reqs.empty()) break;
+            const double t = s->now();
+            for (Req &r : slot.reqs) r.t_launch = t;
+            const int st = launch_slot(s, slot);
+            std::lock_guard<std::mutex> g(s->mu);
+            s->stats.batches++;
+            s->stats.max_batch_requests =
+                std::max<uint64_t>(s->stats.max_batch_requests, slot.reqs.size());
+            if (st != AESGPU_OK) {
+                finish_slot(s, slot, st, s->now());
+            } else {
+                slot.busy = true;
+                in_flight = true;
+            }
+        }
+        // 3. Idle: sleep until a submission or a release; busy: keep polling.
+        if (!in_flight) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait_for(lk, std::chrono::milliseconds(2), [&] {
+                return s->stop.load() || !s->waiting.empty();
+            });
+        } else {
+            std::this_thread::yield();
+        }
+    }
+}
+
+void destroy_server(aesgpu_server *s) {
+    if (s->worker.joinable()) {
+        s->stop.store(true, std::memory_order_release);
+        s->cv.notify_all();
+        s->worker.join();
+    }
+    DeviceGuard g(s->ctx->device);
+    for (Slot &slot : s->slots) {
+        if (slot.stream) (void)hipStreamSynchronize(slot.stream);
+        if (slot.done) (void)hipEventDestroy(slot.done);
+        if (slot.stream) (void)hipStreamDestroy(slot.stream);
+        if (slot.d_buf) (void)hipFree(slot.d_buf);
+        if (slot.h_buf) (void)hipHostFree(slot.h_buf);
+    }
+    if (s->d_sched) (void)hipFree(s->d_sched);
+    if (s->d_arena) (void)hipFree(s->d_arena);
+    delete s;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *key_bits,
+                         size_t n_keys, const aesgpu_server_config *cfg, aesgpu_server **out) {
+    if (!out) return AESGPU_EINVAL;
+    *out = nullptr;
+    if (!ctx || !keys || !key_bits || n_keys == 0 || !cfg) return AESGPU_EINVAL;
+    aesgpu_server_config c = *cfg;
+    if (!c.n_streams) c.n_streams = 4;
+    if (!c.blocks_per_lane) c.blocks_per_lane = 2;
+    if (!c.max_queued) c.max_queued = 1u << 20;
+    if (c.n_streams > 8 || (c.blocks_per_lane != 1 && c.blocks_per_lane != 2) ||
+        c.tile_blocks % (64u * c.blocks_per_lane) || c.arena_bytes < 256 || c.arena_bytes % 256)
+        return AESGPU_EINVAL;
+    // Expand every pool key on the host (encryption and decryption schedules).
+    std::vector<uint32_t> sched(n_keys * kSchedWords, 0u);
+    for (size_t i = 0; i < n_keys; ++i) {
+        aesgpu_key k;
+        const int st = aesgpu_expand_key(keys + 32 * i, key_bits[i] / 8, &k);
+        if (st != AESGPU_OK) return st;
+        std::memcpy(&sched[i * kSchedWords], k.enc, sizeof(k.enc));
+        std::memcpy(&sched[i * kSchedWords + 64], k.dec, sizeof(k.dec));
+    }
+    aesgpu_server *s = new (std::nothrow) aesgpu_server;
+    if (!s) return AESGPU_ENOMEM;
+    s->ctx = ctx;
+    s->cfg = c;
+    s->n_keys = n_keys;
+    s->key_bits.assign(key_bits, key_bits + n_keys);
+    s->arena.capacity = c.arena_bytes;
+    s->arena.granule = 256;
+    s->arena.free_ranges.emplace(0, c.arena_bytes);
+    s->slots.resize(c.n_streams);
+    s->t0 = Clock::now();
+    {
+        DeviceGuard g(ctx->device);
+        bool ok = g.ok();
+        ok = ok && hipMalloc(&s->d_sched, sched.size() * 4) == hipSuccess;
+        ok = ok && hipMemcpy(s->d_sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice) ==
+                       hipSuccess;
+        ok = ok && hipMalloc(&s->d_arena, c.arena_bytes) == hipSuccess;
+        for (Slot &slot : s->slots) {
+            ok = ok && hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) == hipSuccess;
+        }
+        if (!ok) {
+            destroy_server(s);
+            return AESGPU_EHIP;
+        }
+    }
+    try {
+        s->worker = std::thread(worker_main, s);
+    } catch (...) {
+        destroy_server(s);
+        return AESGPU_ENOMEM;
+    }
+    *out = s;
+    return AESGPU_OK;
+}
+
+double aesgpu_server_now(const aesgpu_server *s) { return s ? s->now() : 0.0; }
+
+int aesgpu_server_submit(aesgpu_server *s, uint64_t req_id, int dir, uint32_t key_id,
+                         const void *d_in, size_t n_bytes, double t_arrival) {
+    if (!s) return AESGPU_EINVAL;
+    if (dir != AESGPU_DIR_ENCRYPT && dir != AESGPU_DIR_DECRYPT) return AESGPU_EINVAL;
+    if (key_id >= s->n_keys) return AESGPU_EINVAL;
+    if (n_bytes % 16 || uint64_t(n_bytes) > s->cfg.arena_bytes) return AESGPU_EINVAL;
+    if (n_bytes && !d_in) return AESGPU_EINVAL;
+    if (reinterpret_cast<uintptr_t>(d_in) & 15u) return AESGPU_EALIGN;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (s->fatal != AESGPU_OK) return s->fatal;
+    if (n_bytes == 0) {
+        aesgpu_done d{};
+        d.req_id = req_id;
+        d.t_arrival = t_arrival;
+        d.t_launch = d.t_done = s->now();
+        s->completed.push_back(d);
+        return AESGPU_OK;
+    }
+    if (s->waiting.size() >= s->cfg.max_queued) return AESGPU_EAGAIN;
+    s->waiting.push_back(Req{req_id, key_id, uint8_t(dir), d_in, n_bytes, t_arrival, 0, 0.0});
+    s->stats.requests_submitted++;
+    s->cv.notify_one();
+    return AESGPU_OK;
+}
+
+int aesgpu_server_poll(aesgpu_server *s, aesgpu_done *out, size_t cap, size_t *n_out) {
+    if (!s || !n_out || (cap && !out)) return AESGPU_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    size_t n = 0;
+    while (n < cap && !s->completed.empty()) {
+        out[n++] = s->completed.front();
+        s->completed.pop_front();
+    }
+    *n_out = n;
+    return AESGPU_OK;
+}
+
+int aesgpu_server_release(aesgpu_server *s, const void *d_out, size_t n_bytes) {
+    if (!s) return AESGPU_EINVAL;
+    if (n_bytes == 0) return AESGPU_OK;
+    const uintptr_t p = reinterpret_cast<uintptr_t>(d_out), b = reinterpret_cast<uintptr_t>(s->d_arena);
+    if (p < b || p - b >= s->cfg.arena_bytes) return AESGPU_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    if (!s->arena.release(p - b, n_bytes)) return AESGPU_EINVAL;
+    s->cv.notify_one();
+    return AESGPU_OK;
+}
+
+int aesgpu_server_get_stats(aesgpu_server *s, aesgpu_server_stats *out) {
+    if (!s || !out) return AESGPU_EINVAL;
+    std::lock_guard<std::mutex> g(s->mu);
+    *out = s->stats;
+    out->queued = s->waiting.size();
+    out->arena_used = s->arena.used;
+    out->arena_high_water = s->arena.high_water;
+    return AESGPU_OK;
+}
+
+int aesgpu_server_replay(aesgpu_server *s, const aesgpu_request *reqs, size_t n, double t_start,
+                         aesgpu_done *done) {
+    if (!s || (n && (!reqs || !done))) return AESGPU_EINVAL;
+    std::vector<uint8_t> seen(n, 0);
+    size_t n_done = 0, next = 0;
+    std::vector<aesgpu_done> buf(256);
+    while (n_done < n) {
+        // Submit everything whose arrival time has come.
+        while (next < n && s->now() >= t_start + reqs[next].t_arrival) {
+            const aesgpu_request &r = reqs[next];
+            if (r.req_id >= n) return AESGPU_EINVAL;
+            const int st = aesgpu_server_submit(s, r.req_id, r.dir, r.key_id, r.d_in, r.n_bytes,
+                                                t_start + r.t_arrival);
+            if (st == AESGPU_EAGAIN) break;
+            if (st != AESGPU_OK) return st;
+            ++next;
+        }
+        size_t got = 0;
+        aesgpu_server_poll(s, buf.data(), buf.size(), &got);
+        for (size_t i = 0; i < got; ++i) {
+            const aesgpu_done &d = buf[i];
+            if (d.req_id >= n || seen[d.req_id]) return AESGPU_EINVAL;
+            seen[d.req_id] = 1;
+            done[d.req_id] = d;
+            ++n_done;
+            if (d.n_bytes) aesgpu_server_release(s, d.d_out, d.n_bytes);
+            if (d.status != AESGPU_OK) return d.status;
+        }
+        if (!got) std::this_thread::yield();
+    }
+    return AESGPU_OK;
+}
+
+void aesgpu_server_destroy(aesgpu_server *s) {
+    if (s) destroy_server(s);
+}
+
+}  // extern "C"

@@ -46,3 +46,16 @@ def gather_blocks(dev_u8, idx: np.ndarray) -> np.ndarray:
     blocks = dev_u8.view(-1, 16)
     ix = torch.from_numpy(idx).to(dev_u8.device)
     return blocks.index_select(0, ix).cpu().numpy()
+
+
+def copy_device(dst: int, src: int, n: int) -> None:
+    """Synchronous device-to-device copy of n bytes between raw addresses,
+    through the HIP runtime torch has already loaded."""
+    import ctypes
+
+    import torch  # noqa: F401  (loads the HIP runtime)
+    hip = ctypes.CDLL("libamdhip64.so.7")
+    hip.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+    hip.hipMemcpy.restype = ctypes.c_int
+    rc = hip.hipMemcpy(dst, src, n, 3)  # hipMemcpyDeviceToDevice
+    assert rc == 0, f"hipMemcpy failed: {rc}"

@@ -1,0 +1,95 @@
+"""The server's first-fit range allocator (host logic, no GPU): every offset
+matches a plain first-fit model with coalescing, live ranges never overlap,
+and releases of anything but a live range are rejected."""
+import numpy as np
+import pytest
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1201_0398_amd import aesgpu
+    return aesgpu
+
+
+class FirstFit:
+    """Reference model: a sorted list of free [start, end) ranges."""
+
+    def __init__(self, cap, granule):
+        self.g = granule
+        self.free = [(0, cap)]
+
+    def rnd(self, n):
+        n = max(n, 1)
+        return (n + self.g - 1) // self.g * self.g
+
+    def alloc(self, n):
+        need = self.rnd(n)
+        for i, (a, b) in enumerate(self.free):
+            if b - a >= need:
+                self.free[i:i + 1] = [(a + need, b)] if b - a > need else []
+                return a
+        return None
+
+    def release(self, off, n):
+        self.free.append((off, off + self.rnd(n)))
+        self.free.sort()
+        merged = []
+        for a, b in self.free:
+            if merged and merged[-1][1] == a:
+                merged[-1] = (merged[-1][0], b)
+            else:
+                merged.append((a, b))
+        self.free = merged
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_matches_first_fit_model(A, seed):
+    rng = np.random.default_rng(seed)
+    cap, g = 1 << 20, 256
+    arena = A.aesgpu_arena_create(cap, g)
+    model = FirstFit(cap, g)
+    live = {}
+    try:
+        for step in range(3000):
+            if live and (rng.random() < 0.45 or len(live) > 200):
+                off = list(live)[int(rng.integers(0, len(live)))]
+                n = live.pop(off)
+                A.aesgpu_arena_release(arena, off, n)
+                model.release(off, n)
+            else:
+                n = int(rng.integers(1, 40000))
+                got = A.aesgpu_arena_alloc(arena, n)
+                want = model.alloc(n)
+                assert got == want, f"step {step}"
+                if got is not None:
+                    live[got] = n
+            spans = sorted((o, o + model.rnd(n)) for o, n in live.items())
+            assert all(spans[i][1] <= spans[i + 1][0] for i in range(len(spans) - 1))
+            used, largest, _ = A.aesgpu_arena_query(arena)
+            assert used == sum(model.rnd(n) for n in live.values())
+            assert largest == max([b - a for a, b in model.free], default=0)
+    finally:
+        A.aesgpu_arena_destroy(arena)
+
+
+def test_errors_and_coalescing(A):
+    arena = A.aesgpu_arena_create(4096, 256)
+    try:
+        a, b, c = (A.aesgpu_arena_alloc(arena, n) for n in (1000, 256, 2000))
+        assert (a, b, c) == (0, 1024, 1280)
+        assert A.aesgpu_arena_alloc(arena, 1024) is None              # EAGAIN: full for now
+        with pytest.raises(A.AesgpuError):
+            A.aesgpu_arena_alloc(arena, 8192)                         # never fits
+        assert A.aesgpu_arena_release(arena, 512, 256, check=False) == A.AESGPU_EINVAL
+        A.aesgpu_arena_release(arena, b, 256)
+        assert A.aesgpu_arena_release(arena, b, 256, check=False) == A.AESGPU_EINVAL  # twice
+        A.aesgpu_arena_release(arena, a, 1000)
+        assert A.aesgpu_arena_query(arena)[1] == 1280                 # 0..1280 coalesced
+        A.aesgpu_arena_release(arena, c, 2000)
+        assert A.aesgpu_arena_query(arena)[:2] == (0, 4096)
+        assert A.aesgpu_arena_query(arena)[2] == 3328
+    finally:
+        A.aesgpu_arena_destroy(arena)
+    for cap, g in ((1000, 256), (4096, 100), (0, 256)):
+        with pytest.raises(A.AesgpuError):
+            A.aesgpu_arena_create(cap, g)

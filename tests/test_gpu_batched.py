@@ -62,7 +62,7 @@ def _plan(A, ctx, b, **kw):
     return A.aesgpu_batch_plan(ctx, msgs, **kw)
 
 
-@pytest.mark.parametrize("bpl,tile", [(4, 2048), (2, 128), (4, 256)])
+@pytest.mark.parametrize("bpl,tile", [(1, 2048), (2, 128), (2, 8192), (1, 64)])
 def test_mixed_batch_matches_oracle(A, ctx, bpl, tile):
     import torch
     rng = np.random.default_rng(30 + bpl + tile)
@@ -71,7 +71,8 @@ def test_mixed_batch_matches_oracle(A, ctx, bpl, tile):
     plan = _plan(A, ctx, b, blocks_per_lane=bpl, tile_blocks=tile)
     try:
         st = A.aesgpu_batch_info(plan)
-        assert st.n_msgs == 300 and st.launches == 2
+        assert st.n_msgs == 300 and st.launches == 1
+        assert st.n_tiles_forward > 0 and st.n_tiles_inverse > 0
         d_keys = to_dev(b["keys"].reshape(-1))
         d_in = to_dev(b["data"])
         d_out = torch.full((b["total"],), 0x5A, dtype=torch.uint8, device="cuda")
