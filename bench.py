@@ -119,11 +119,16 @@ def batched_bench(torch, A, ctx, rates: dict, reps: int) -> dict:
     m = w.lengths.size
     msgs = A.make_msgs(w.offsets, w.offsets, w.lengths, np.arange(m), w.key_bits, w.modes,
                        np.zeros(m, dtype=np.int64), w.nonces, w.ctr0)
-    plan = A.aesgpu_batch_plan(ctx, msgs)
-    info = A.aesgpu_batch_info(plan)
     d_keys = torch.from_numpy(w.keys.reshape(-1).copy()).to("cuda")
     d_in = torch.from_numpy(w.data.copy()).to("cuda")
     d_out = torch.empty_like(d_in)
+    from paper_1201_0398_amd import autotune
+    log("autotuning the batch launch shape")
+    choice = autotune.tune_batch(ctx, msgs, w.lengths, w.modes, np.zeros(m, dtype=np.int64),
+                                 d_keys, m, d_in, d_out, reps=2, use_cache=False)
+    plan = A.aesgpu_batch_plan(ctx, msgs, blocks_per_lane=choice.blocks_per_lane,
+                               tile_blocks=choice.tile_blocks)
+    info = A.aesgpu_batch_info(plan)
     log(f"timing the batch: {m} messages, {w.total_bytes} bytes")
     sec = time_call(torch, lambda: A.aesgpu_batch_run(plan, d_keys, m, d_in, d_out), reps)
     # Reference time: every message at the single-buffer rate of its key size and mode.
@@ -136,6 +141,7 @@ def batched_bench(torch, A, ctx, rates: dict, reps: int) -> dict:
             "messages": m, "bytes": int(w.total_bytes),
             "tiles": int(info.n_tiles_forward + info.n_tiles_inverse),
             "tile_blocks": int(info.tile_blocks), "blocks_per_lane": int(info.blocks_per_lane),
+            "autotune_ms": choice.timings,
             "time_vs_single_buffer_mix": round(sec / t_ref, 3),
             "time_vs_single_buffer_aes128_ecb": round(sec / t_128, 3),
             "workload": "65,536 messages, log-uniform 16 B..1 MiB, own key each, key size "
