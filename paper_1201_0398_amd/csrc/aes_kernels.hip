@@ -15,6 +15,14 @@
 //  * Decryption adds InvS (replicated into all four bytes of a word) at
 //    131072 + x * 128 + 4c, 32 KiB, for the last round: 160 KiB in total.
 //  * Round keys are kernel arguments, so they are loaded once into SGPRs.
+//  * CTR (32-bit big-endian counter): lane L of a tile holds blocks
+//    L * BPL .. L * BPL + BPL - 1 (lane-major), and the mapping is shifted by
+//    ctr0 mod (64 * BPL) so that every wave holds 64 * BPL <= 256 consecutive
+//    counters starting at a multiple of 64 * BPL.  Then only the low byte of
+//    the counter differs across the wave: three of the four round-1 lookups
+//    and twelve of the sixteen round-2 lookups have wave-uniform indices and
+//    are read once per wave and tile through the scalar cache, leaving 5 LDS
+//    lookups per block for the first two rounds.
 //  * 1024 threads per workgroup and one workgroup per CU (the tables take the
 //    whole LDS); the grid is at most one workgroup per CU and strides over
 //    tiles of 1024 * BPL blocks.
@@ -38,74 +46,199 @@ struct Params {
     uint32_t ctr0;
     const uint32_t *tables;
     uint64_t index0;        // LE-128 counter offset
+    uint32_t voff;          // virtual index = block index + voff (CTR: ctr0 mod 64 * BPL)
     uint32_t iv[4];
     CtrConsts cc;
     RoundKeys rk;
 };
 
-// Blocks base + j * kWG + threadIdx.x (j < BPL) that are below n_full; zero
-// for the others.
-template <int BPL>
-__device__ __forceinline__ void load_tile(uint4 (&v)[BPL], const uint4 *in, uint64_t base,
-                                          uint64_t n_full) {
+// Position of slot j of this lane inside a tile of kWG * BPL blocks: slot-major
+// (each wave instruction touches 64 consecutive blocks) or lane-major (each
+// lane holds BPL consecutive blocks).
+template <bool kLaneMajor, int BPL>
+__device__ __forceinline__ uint32_t tile_slot(int j) {
+    return kLaneMajor ? threadIdx.x * BPL + uint32_t(j) : uint32_t(j) * kWG + threadIdx.x;
+}
+
+// Block index of slot j of this lane in the tile at virtual position base.
+// Lanes before the first block wrap to huge values and fail every range test.
+template <bool kLaneMajor, int BPL>
+__device__ __forceinline__ uint64_t block_index(uint64_t base, int j, uint32_t voff) {
+    return base + tile_slot<kLaneMajor, BPL>(j) - voff;
+}
+
+// Buffer resources for the tile at virtual position base.  A raw buffer
+// access whose offset lies past the resource's range reads zero or writes
+// nothing (the hardware checks it), so every lane issues its loads and
+// stores without a branch, and the compiler can count them exactly when it
+// places the waits that let the next tile's loads overlap this tile's rounds.
+// The resource starts at the tile's first real block and covers the blocks
+// of the tile that exist; lanes before block 0 get offsets that wrap to
+// values far past any range.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+constexpr int kRawBufferWord3 = 0x00020000;   // gfx9 raw buffer, 32-bit data format
+
+struct TileView {
+    rsrc_t in, out;
+    uint32_t shift;   // lanes before block 0 in this tile (first tile only)
+};
+
+__device__ __forceinline__ TileView tile_view(const uint4 *in, uint4 *out, uint64_t base,
+                                              uint64_t n_full, uint32_t voff, uint32_t tile) {
+    const uint64_t first = base >= voff ? base - voff : 0;
+    const uint32_t shift = base >= voff ? 0u : voff;
+    const uint64_t left = first < n_full ? n_full - first : 0;
+    const int range = int(16u * uint32_t(left < tile ? left : tile));
+    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(in + first), 0, range,
+                                              kRawBufferWord3),
+            __builtin_amdgcn_make_buffer_rsrc(out + first, 0, range, kRawBufferWord3), shift};
+}
+
+template <bool kLaneMajor, int BPL>
+__device__ __forceinline__ uint32_t lane_offset(const TileView &v, int j) {
+    return (tile_slot<kLaneMajor, BPL>(j) - v.shift) * 16u;
+}
+
+template <bool kLaneMajor, int BPL>
+__device__ __forceinline__ void load_tile(uint4 (&v)[BPL], const TileView &t) {
 #pragma unroll
     for (int j = 0; j < BPL; ++j) {
-        const uint64_t idx = base + uint64_t(j) * kWG + threadIdx.x;
-        v[j] = make_uint4(0, 0, 0, 0);
-        if (idx < n_full) v[j] = in[idx];
+        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(
+            t.in, lane_offset<kLaneMajor, BPL>(t, j), 0, 0);
+        v[j] = make_uint4(x[0], x[1], x[2], x[3]);
+    }
+}
+
+template <bool kLaneMajor, int BPL>
+__device__ __forceinline__ void store_block(const TileView &t, int j, const uint4 &o) {
+    const u32x4 x = {o.x, o.y, o.z, o.w};
+    __builtin_amdgcn_raw_buffer_store_b128(x, t.out, lane_offset<kLaneMajor, BPL>(t, j), 0, 0);
+}
+
+// Pointers into the constant address space: a load through one with a
+// wave-uniform address is a scalar load through the scalar cache.  Only for
+// memory that no kernel in flight writes.
+template <class T>
+__device__ __forceinline__ const T __attribute__((address_space(4))) *as_const(const T *p) {
+    return (const T __attribute__((address_space(4))) *)p;
+}
+
+// T_t[x] from the table copy in device memory, for an index that is the same
+// in every lane: one scalar load instead of an LDS instruction.
+__device__ __forceinline__ uint32_t tab_u(const uint32_t *te, uint32_t t, uint32_t x) {
+    return as_const(te)[__builtin_amdgcn_readfirstlane(t * 256u + x)];
+}
+
+__device__ __forceinline__ uint32_t byte_of(uint32_t w, int k) { return (w >> (8 * k)) & 0xFFu; }
+
+// Whitened counter block (round 0 done) of block idx for the CTR modes.
+template <Op OP>
+__device__ __forceinline__ void counter_state(const Params &p, uint64_t idx, uint32_t (&s)[4]) {
+    if constexpr (OP == Op::kCtrBe32) {
+        // nonce words 0..2, word 3 = BE32(ctr0 + idx)
+        s[0] = p.cc.x0[0];
+        s[1] = p.cc.x0[1];
+        s[2] = p.cc.x0[2];
+        s[3] = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.k03;
+    } else {
+        // IV + index0 + idx as a 128-bit little-endian integer
+        const uint64_t add = p.index0 + idx;
+        const uint64_t lo0 = uint64_t(p.iv[0]) | (uint64_t(p.iv[1]) << 32);
+        const uint64_t hi0 = uint64_t(p.iv[2]) | (uint64_t(p.iv[3]) << 32);
+        const uint64_t lo = lo0 + add;
+        const uint64_t hi = hi0 + (lo < lo0 ? 1u : 0u);
+        s[0] = uint32_t(lo) ^ p.rk.w[0];
+        s[1] = uint32_t(lo >> 32) ^ p.rk.w[1];
+        s[2] = uint32_t(hi) ^ p.rk.w[2];
+        s[3] = uint32_t(hi >> 32) ^ p.rk.w[3];
     }
 }
 
 template <Op OP, int NR, int BPL>
 __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
+    constexpr bool kCtr = (OP == Op::kCtrBe32 || OP == Op::kCtrLe128);
+    constexpr bool kLM = (OP == Op::kCtrBe32);   // lane-major tiles
     __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords];
     stage_tables<kInv>(lds, p.tables);
     const Bases b = lane_bases();
 
-    const uint64_t n_total = p.n_full + (p.tail ? 1 : 0);
+    // The loop covers the whole blocks; a CTR tail is finished after it.
+    const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
     const uint64_t tile = uint64_t(kWG) * BPL;
     const uint64_t stride = uint64_t(gridDim.x) * tile;
+    const uint32_t wave_first = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
     // The blocks of the next tile are loaded while the current one is
     // computed, so HBM latency overlaps the rounds even at low occupancy.
     uint4 next[BPL];
-    load_tile<BPL>(next, p.in, uint64_t(blockIdx.x) * tile, p.n_full);
-    for (uint64_t base = uint64_t(blockIdx.x) * tile; base < n_total; base += stride) {
+    TileView view = tile_view(p.in, p.out, uint64_t(blockIdx.x) * tile, p.n_full, p.voff, tile);
+    load_tile<kLM, BPL>(next, view);
+    // In the loop a tile's loads are followed by the previous tile's stores,
+    // and the loop top waits for the loads only.  These stores have an empty
+    // range and write nothing; they give the loop entry the same order, so
+    // that wait does not also cover the last stores on every iteration.
+    {
+        const rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(p.out, 0, 0, kRawBufferWord3);
+        const u32x4 zero = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int j = 0; j < BPL; ++j)
+            __builtin_amdgcn_raw_buffer_store_b128(zero, none, lane_offset<kLM, BPL>(view, j), 0,
+                                                   0);
+    }
+    for (uint64_t base = uint64_t(blockIdx.x) * tile; base < v_end; base += stride) {
         uint32_t s[BPL][4];
         uint4 in[BPL];
 #pragma unroll
         for (int j = 0; j < BPL; ++j) in[j] = next[j];
-        load_tile<BPL>(next, p.in, base + stride, p.n_full);
+        const TileView cur = view;
+        view = tile_view(p.in, p.out, base + stride, p.n_full, p.voff, tile);
+        load_tile<kLM, BPL>(next, view);
+        // CTR rounds 1 and 2.  Round 1: output word c needs one lookup, on
+        // byte (3 - c) of counter word 3; the other three terms are
+        // constants.  The wave's counters share all but their low byte, so
+        // bytes 0..2 of word 3 and round-1 words 1..3 are wave-uniform
+        // (scalar); only word 0 differs per block.  Round 2 (Eq. (1) with
+        // round key 2): each output word has one term on word 0 (per block)
+        // and three on words 1..3 (uniform).
+        uint32_t c[4] = {0, 0, 0, 0};
+        if constexpr (OP == Op::kCtrBe32) {
+            const uint32_t ctr_first = p.ctr0 - p.voff + uint32_t(base) + wave_first * BPL;
+            const uint32_t w3u = bswap32(ctr_first) ^ p.cc.k03;
+            const uint32_t *te = p.tables + kTe;
+            const uint32_t u1 = p.cc.p[1] ^ tab_u(te, 2, byte_of(w3u, 2));
+            const uint32_t u2 = p.cc.p[2] ^ tab_u(te, 1, byte_of(w3u, 1));
+            const uint32_t u3 = p.cc.p[3] ^ tab_u(te, 0, byte_of(w3u, 0));
+            const uint32_t *k2 = &p.rk.w[8];
+            c[0] = tab_u(te, 1, byte_of(u1, 1)) ^ tab_u(te, 2, byte_of(u2, 2)) ^
+                   tab_u(te, 3, byte_of(u3, 3)) ^ k2[0];
+            c[1] = tab_u(te, 0, byte_of(u1, 0)) ^ tab_u(te, 1, byte_of(u2, 1)) ^
+                   tab_u(te, 2, byte_of(u3, 2)) ^ k2[1];
+            c[2] = tab_u(te, 0, byte_of(u2, 0)) ^ tab_u(te, 1, byte_of(u3, 1)) ^
+                   tab_u(te, 3, byte_of(u1, 3)) ^ k2[2];
+            c[3] = tab_u(te, 0, byte_of(u3, 0)) ^ tab_u(te, 2, byte_of(u1, 2)) ^
+                   tab_u(te, 3, byte_of(u2, 3)) ^ k2[3];
+        }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
-            const uint64_t idx = base + uint64_t(j) * kWG + threadIdx.x;
+            const uint64_t idx = block_index<kLM, BPL>(base, j, p.voff);
             if constexpr (OP == Op::kEcbEnc || OP == Op::kEcbDec || OP == Op::kCbcDec) {
                 s[j][0] = in[j].x ^ p.rk.w[0];
                 s[j][1] = in[j].y ^ p.rk.w[1];
                 s[j][2] = in[j].z ^ p.rk.w[2];
                 s[j][3] = in[j].w ^ p.rk.w[3];
             } else if constexpr (OP == Op::kCtrBe32) {
-                // Counter block: nonce words 0..2, word 3 = BE32(ctr0 + idx).
-                // Round 1 is done here: output word c needs one lookup, on
-                // byte (3 - c) of word 3; the other three terms are constants.
                 const uint32_t w3 = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.k03;
-                s[j][0] = p.cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
-                s[j][1] = p.cc.p[1] ^ tlook<2>(lds, w3, b.t[2]);
-                s[j][2] = p.cc.p[2] ^ tlook<1>(lds, w3, b.t[1]);
-                s[j][3] = p.cc.p[3] ^ tlook<0>(lds, w3, b.t[0]);
-            } else {  // kCtrLe128: IV + index0 + idx as a 128-bit LE integer
-                const uint64_t add = p.index0 + idx;
-                const uint64_t lo0 = uint64_t(p.iv[0]) | (uint64_t(p.iv[1]) << 32);
-                const uint64_t hi0 = uint64_t(p.iv[2]) | (uint64_t(p.iv[3]) << 32);
-                const uint64_t lo = lo0 + add;
-                const uint64_t hi = hi0 + (lo < lo0 ? 1u : 0u);
-                s[j][0] = uint32_t(lo) ^ p.rk.w[0];
-                s[j][1] = uint32_t(lo >> 32) ^ p.rk.w[1];
-                s[j][2] = uint32_t(hi) ^ p.rk.w[2];
-                s[j][3] = uint32_t(hi >> 32) ^ p.rk.w[3];
+                const uint32_t v0 = p.cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
+                s[j][0] = tlook<0>(lds, v0, b.t[0]) ^ c[0];
+                s[j][1] = tlook<3>(lds, v0, b.t[3]) ^ c[1];
+                s[j][2] = tlook<2>(lds, v0, b.t[2]) ^ c[2];
+                s[j][3] = tlook<1>(lds, v0, b.t[1]) ^ c[3];
+            } else {
+                counter_state<OP>(p, idx, s[j]);
             }
         }
-        const int first = (OP == Op::kCtrBe32) ? 2 : 1;
+        const int first = (OP == Op::kCtrBe32) ? 3 : 1;
 #pragma unroll
         for (int r = 1; r < NR; ++r) {
             if (r < first) continue;
@@ -121,41 +254,60 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
-            const uint64_t idx = base + uint64_t(j) * kWG + threadIdx.x;
             uint4 o = make_uint4(s[j][0], s[j][1], s[j][2], s[j][3]);
-            if constexpr (OP == Op::kCtrBe32 || OP == Op::kCtrLe128) {
+            if constexpr (kCtr) {
                 o.x ^= in[j].x;
                 o.y ^= in[j].y;
                 o.z ^= in[j].z;
                 o.w ^= in[j].w;
             } else if constexpr (OP == Op::kCbcDec) {
-                // Eq. (2): XOR with the previous ciphertext block (IV first).
-                uint4 prev = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
-                if (idx > 0 && idx < p.n_full) prev = p.in[idx - 1];
-                o.x ^= prev.x;
-                o.y ^= prev.y;
-                o.z ^= prev.z;
-                o.w ^= prev.w;
+                // Eq. (2): XOR with the previous ciphertext block.  Lane L > 0
+                // of a wave takes it from lane L - 1 (a DPP shift of the
+                // wave); lane 0's comes from the IV or a scalar load.
+                const uint64_t first_idx = base + uint64_t(j) * kWG + wave_first;
+                uint4 prev0 = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
+                if (first_idx > 0) {
+                    const uint64_t q = first_idx - 1 < p.n_full ? first_idx - 1 : p.n_full - 1;
+                    const auto *w = as_const(reinterpret_cast<const uint32_t *>(p.in + q));
+                    prev0 = make_uint4(w[0], w[1], w[2], w[3]);
+                }
+                o.x ^= __builtin_amdgcn_update_dpp(prev0.x, in[j].x, 0x138, 0xf, 0xf, false);
+                o.y ^= __builtin_amdgcn_update_dpp(prev0.y, in[j].y, 0x138, 0xf, 0xf, false);
+                o.z ^= __builtin_amdgcn_update_dpp(prev0.z, in[j].z, 0x138, 0xf, 0xf, false);
+                o.w ^= __builtin_amdgcn_update_dpp(prev0.w, in[j].w, 0x138, 0xf, 0xf, false);
             }
-            if (idx < p.n_full) {
-                p.out[idx] = o;
-            } else if (idx == p.n_full && p.tail) {
-                // Partial last block of a CTR call: byte-wise, only in range.
+            store_block<kLM, BPL>(cur, j, o);
+        }
+    }
+    if constexpr (kCtr) {
+        // Partial last block: wave 0 of workgroup 0 computes its keystream
+        // (the same block in every lane) and lane q < tail writes byte q.
+        if (p.tail && blockIdx.x == 0 && threadIdx.x < 64) {
+            uint32_t s[4];
+            counter_state<OP>(p, p.n_full, s);
+#pragma unroll
+            for (int r = 1; r < NR; ++r) mid_round<false>(lds, b, s, &p.rk.w[4 * r]);
+            last_round_fwd(lds, b, s, &p.rk.w[4 * NR]);
+            const uint32_t q = threadIdx.x;
+            if (q < p.tail) {
                 const uint8_t *src = reinterpret_cast<const uint8_t *>(p.in + p.n_full);
                 uint8_t *dst = reinterpret_cast<uint8_t *>(p.out + p.n_full);
-                const uint32_t ks[4] = {s[j][0], s[j][1], s[j][2], s[j][3]};
-                for (uint32_t q = 0; q < p.tail; ++q)
-                    dst[q] = src[q] ^ uint8_t(ks[q >> 2] >> (8 * (q & 3)));
+                const uint32_t w = q < 4 ? s[0] : q < 8 ? s[1] : q < 12 ? s[2] : s[3];
+                dst[q] = src[q] ^ uint8_t(w >> (8 * (q & 3)));
             }
         }
     }
 }
 
 template <Op OP, int NR, int BPL>
-int launch_one(const Params &p, int n_cu, hipStream_t stream) {
-    const uint64_t n_total = p.n_full + (p.tail ? 1 : 0);
-    const uint64_t tiles = (n_total + uint64_t(kWG) * BPL - 1) / (uint64_t(kWG) * BPL);
-    const uint32_t grid = uint32_t(tiles < uint64_t(n_cu) ? tiles : uint64_t(n_cu));
+int launch_one(Params p, int n_cu, hipStream_t stream) {
+    // CTR: shift the mapping so every wave's 64 * BPL counters start at a
+    // multiple of 64 * BPL.
+    p.voff = OP == Op::kCtrBe32 ? (p.ctr0 & (64u * BPL - 1u)) : 0u;
+    // At least one workgroup: a CTR call shorter than a block has only a tail.
+    const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
+    const uint64_t tiles = (v_end + uint64_t(kWG) * BPL - 1) / (uint64_t(kWG) * BPL);
+    const uint32_t grid = tiles == 0 ? 1u : uint32_t(tiles < uint64_t(n_cu) ? tiles : uint64_t(n_cu));
     hipLaunchKernelGGL((aes_kernel<OP, NR, BPL>), dim3(grid), dim3(kWG), 0, stream, p);
     return hipGetLastError() == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
 }

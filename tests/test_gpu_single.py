@@ -123,6 +123,40 @@ def test_ctr_lengths_and_counters(A, ctx, kb):
             assert (out[n_bytes:] == 0x5A).all(), "wrote past the end"
 
 
+@pytest.mark.parametrize("kb", [16, 32])
+def test_ctr_counter_alignment_and_carries(A, ctx, kb):
+    """Counters at every offset modulo 64 that the lane mapping shifts by, and
+    runs that carry into bytes 1, 2 and 3 of the 32-bit counter mid-call."""
+    import torch
+    rng = np.random.default_rng(2500 + kb)
+    key = rng.integers(0, 256, kb, dtype=np.uint8)
+    k = A.aesgpu_expand_key(key)
+    n_bytes = 16 * (2 * TILE + 300) + 7
+    n_blocks = (n_bytes + 15) // 16
+    starts = [0, 63, 64, 65, 127, 0xFF - 40, 0xFFFF - 5000, 0xFFFFFF - 70000,
+              (1 << 32) - n_blocks - 1]
+    for ctr0 in starts:
+        log(f"case: CTR-{8 * kb} n_bytes={n_bytes} ctr0={ctr0:#x}")
+        nonce = rng.integers(0, 256, 12, dtype=np.uint8)
+        data = rng.integers(0, 256, n_bytes, dtype=np.uint8)
+        d_in = to_dev(data)
+        d_out = torch.full((n_bytes + 64,), 0x5A, dtype=torch.uint8, device="cuda")
+        A.aesgpu_ctr_xcrypt(ctx, k, nonce, ctr0, d_in, d_out, n_bytes)
+        out = from_dev(d_out)
+        assert np.array_equal(out[:n_bytes], oracle.ctr(key, nonce, ctr0, data))
+        assert (out[n_bytes:] == 0x5A).all(), "wrote past the end"
+    for n_bytes in [1, 16 * 63, 16 * 64 + 1, 16 * 65]:       # less than one wave
+        for ctr0 in [0, 1, 62, 63]:
+            nonce = rng.integers(0, 256, 12, dtype=np.uint8)
+            data = rng.integers(0, 256, n_bytes, dtype=np.uint8)
+            d_in = to_dev(data)
+            d_out = torch.full((n_bytes + 64,), 0x5A, dtype=torch.uint8, device="cuda")
+            A.aesgpu_ctr_xcrypt(ctx, k, nonce, ctr0, d_in, d_out, n_bytes)
+            out = from_dev(d_out)
+            assert np.array_equal(out[:n_bytes], oracle.ctr(key, nonce, ctr0, data)), (n_bytes, ctr0)
+            assert (out[n_bytes:] == 0x5A).all(), "wrote past the end"
+
+
 def test_ctr_involution_chunking_and_overflow(A, ctx):
     import torch
     rng = np.random.default_rng(3)
