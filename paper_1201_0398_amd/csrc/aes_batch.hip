@@ -150,6 +150,31 @@ __device__ __forceinline__ uint32_t schedule_of(const uint32_t *lds, const Bases
 // unrolled and takes nr at run time: one short loop body serves all key
 // sizes, so the code a workgroup runs fits the instruction cache even when
 // each CU executes it only once (small batches).
+// A descriptor read through the scalar cache, word by word.
+template <class T>
+__device__ __forceinline__ T load_uniform(const T *src) {
+    static_assert(sizeof(T) % 4 == 0, "descriptor size");
+    T v;
+    const auto *w = as_const(reinterpret_cast<const uint32_t *>(src));
+    uint32_t *d = reinterpret_cast<uint32_t *>(&v);
+#pragma unroll
+    for (unsigned i = 0; i < sizeof(T) / 4; ++i) d[i] = w[i];
+    return v;
+}
+
+// Round 1 of a CTR counter block (nonce words 0..2, word 3 = BE32(ctr)),
+// from the per-message constants: output word c needs one lookup, on byte
+// (3 - c) of word 3; the other three terms are constants.
+__device__ __forceinline__ void counter_round1(const uint32_t *lds, const Bases &b,
+                                               const CtrConsts &cc, uint32_t ctr,
+                                               uint32_t (&s)[4]) {
+    const uint32_t w3 = bswap32(ctr) ^ cc.k03;
+    s[0] = cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
+    s[1] = cc.p[1] ^ tlook<2>(lds, w3, b.t[2]);
+    s[2] = cc.p[2] ^ tlook<1>(lds, w3, b.t[1]);
+    s[3] = cc.p[3] ^ tlook<0>(lds, w3, b.t[0]);
+}
+
 template <bool kInv, int BPL>
 __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, const BatchParams &p,
                                          const DevMsg &m, const Tile &tile) {
@@ -192,21 +217,35 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     const uint32_t lane = threadIdx.x & 63u;
     const uint4 *in = reinterpret_cast<const uint4 *>(p.in + m.in_off);
     uint4 *out = reinterpret_cast<uint4 *>(p.out + m.out_off);
-    const uint64_t end = tile.first_block + tile.n_blocks;
+    const uint64_t first = tile.first_block;
+    const uint64_t end = first + tile.n_blocks;
     constexpr uint32_t kStep = 64u * BPL;
     const uint64_t lim = end < m.n_full ? end : m.n_full;  // whole blocks of this tile
-    // The next step's blocks are loaded while the current step is computed.
+    // Buffer resources over the tile's whole blocks: loads past them read
+    // zero and stores past them are dropped, so no lane branches and the
+    // compiler can wait for exactly the older loads (the next step's blocks
+    // are loaded while the current step is computed).
+    const uint32_t bytes = lim > first ? 16u * uint32_t(lim - first) : 0u;
+    const rsrc_t rin = buffer_rsrc(in + first, bytes);
+    const rsrc_t rout = buffer_rsrc(out + first, bytes);
     uint4 next[BPL];
 #pragma unroll
-    for (int j = 0; j < BPL; ++j) {
-        const uint64_t idx = tile.first_block + uint64_t(j) * 64u + lane;
-        next[j] = make_uint4(0, 0, 0, 0);
-        if (idx < lim) next[j] = in[idx];
+    for (int j = 0; j < BPL; ++j) next[j] = buffer_load16(rin, (uint32_t(j) * 64u + lane) * 16u);
+    {
+        // In the loop a step's loads are followed by the previous step's
+        // stores.  These stores have an empty range and write nothing; they
+        // give the loop entry the same order, so the wait at the top of the
+        // loop covers the loads only.
+        const rsrc_t none = buffer_rsrc(out, 0);
+#pragma unroll
+        for (int j = 0; j < BPL; ++j)
+            buffer_store16(none, (uint32_t(j) * 64u + lane) * 16u, make_uint4(0, 0, 0, 0));
     }
-    for (uint64_t base = tile.first_block; base < end; base += kStep) {
+    for (uint64_t base = first; base < lim; base += kStep) {
         // Keep the round-key reads inside the loop: hoisting all of them would
         // need 4 * (nr + 1) SGPRs at once.
         asm volatile("" : "+v"(kreg));
+        const uint32_t step_off = uint32_t(base - first);
         uint32_t s[BPL][4];
         uint4 d[BPL];
         uint32_t rk[4];
@@ -214,21 +253,13 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             d[j] = next[j];
-            const uint64_t nidx = base + kStep + uint64_t(j) * 64u + lane;
-            next[j] = make_uint4(0, 0, 0, 0);
-            if (nidx < lim) next[j] = in[nidx];
+            next[j] = buffer_load16(rin, (step_off + kStep + uint32_t(j) * 64u + lane) * 16u);
         }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             const uint64_t idx = base + uint64_t(j) * 64u + lane;
             if (ctr) {
-                const uint32_t w3 = __builtin_amdgcn_perm(m.ctr0 + uint32_t(idx),
-                                                          m.ctr0 + uint32_t(idx), 0x00010203u) ^
-                                    cc.k03;
-                s[j][0] = cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
-                s[j][1] = cc.p[1] ^ tlook<2>(lds, w3, b.t[2]);
-                s[j][2] = cc.p[2] ^ tlook<1>(lds, w3, b.t[1]);
-                s[j][3] = cc.p[3] ^ tlook<0>(lds, w3, b.t[0]);
+                counter_round1(lds, b, cc, m.ctr0 + uint32_t(idx), s[j]);
             } else {
                 s[j][0] = d[j].x ^ rk[0];
                 s[j][1] = d[j].y ^ rk[1];
@@ -257,8 +288,6 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
         }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
-            const uint64_t idx = base + uint64_t(j) * 64u + lane;
-            if (idx >= end) continue;
             uint4 o = make_uint4(s[j][0], s[j][1], s[j][2], s[j][3]);
             if (ctr) {
                 o.x ^= d[j].x;
@@ -266,14 +295,28 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                 o.z ^= d[j].z;
                 o.w ^= d[j].w;
             }
-            if (idx < m.n_full) {
-                out[idx] = o;
-            } else if (ctr && idx == m.n_full && m.tail) {
+            buffer_store16(rout, (step_off + uint32_t(j) * 64u + lane) * 16u, o);
+        }
+    }
+    if constexpr (!kInv) {
+        // Partial last block of a CTR message (it lies in the message's last
+        // tile): every lane computes its keystream, lane q < tail writes byte q.
+        if (ctr && m.tail && end > m.n_full) {
+            uint32_t s[4];
+            uint32_t rk[4];
+            counter_round1(lds, b, cc, m.ctr0 + uint32_t(m.n_full), s);
+#pragma unroll 1
+            for (uint32_t r = 2; r < nr; ++r) {
+                round_key(kreg, r, rk);
+                mid_round<false>(lds, b, s, rk);
+            }
+            round_key(kreg, nr, rk);
+            last_round_fwd(lds, b, s, rk);
+            if (lane < m.tail) {
                 const uint8_t *src = reinterpret_cast<const uint8_t *>(in + m.n_full);
                 uint8_t *dst = reinterpret_cast<uint8_t *>(out + m.n_full);
-                const uint32_t ks[4] = {s[j][0], s[j][1], s[j][2], s[j][3]};
-                for (uint32_t q = 0; q < m.tail; ++q)
-                    dst[q] = src[q] ^ uint8_t(ks[q >> 2] >> (8 * (q & 3)));
+                const uint32_t w = lane < 4 ? s[0] : lane < 8 ? s[1] : lane < 12 ? s[2] : s[3];
+                dst[lane] = src[lane] ^ uint8_t(w >> (8 * (lane & 3u)));
             }
         }
     }
@@ -293,6 +336,7 @@ __device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
     const Tile *__restrict__ tiles = p.tiles[set];
     uint32_t t = first;
     for (;;) {
+        t = __builtin_amdgcn_readfirstlane(t);
         if (t == kNone) {
             if (p.n_static[set] >= p.n_tiles[set]) break;  // no dynamic tiles at all
             uint32_t c = 0;
@@ -300,8 +344,10 @@ __device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
             t = p.n_static[set] + __builtin_amdgcn_readfirstlane(c);
         }
         if (t >= p.n_tiles[set]) break;
-        const Tile tile = tiles[t];
-        const DevMsg m = msgs[tile.msg];
+        // Scalar loads (the index is wave-uniform and nothing writes the
+        // descriptors during a launch), so every field is uniform.
+        const Tile tile = load_uniform(tiles + t);
+        const DevMsg m = load_uniform(msgs + tile.msg);
         run_tile<kInv, BPL>(lds, b, p, m, tile);
         t = kNone;
     }

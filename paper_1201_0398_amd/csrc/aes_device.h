@@ -160,5 +160,36 @@ __device__ __forceinline__ uint32_t bswap32(uint32_t v) {
     return __builtin_amdgcn_perm(v, v, 0x00010203u);
 }
 
+// Raw buffer accesses.  The hardware checks each offset against the
+// resource's range: past it a load reads zero and a store writes nothing.
+// Kernels use them for block loads and stores so that no lane needs a branch
+// and the compiler can count the outstanding memory operations exactly.
+using rsrc_t = __amdgpu_buffer_rsrc_t;
+using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
+constexpr int kRawBufferWord3 = 0x00020000;   // gfx9 raw buffer, 32-bit data format
+
+__device__ __forceinline__ rsrc_t buffer_rsrc(const void *base, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), 0, int(bytes),
+                                             kRawBufferWord3);
+}
+
+__device__ __forceinline__ uint4 buffer_load16(rsrc_t r, uint32_t offset) {
+    const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, offset, 0, 0);
+    return make_uint4(x[0], x[1], x[2], x[3]);
+}
+
+__device__ __forceinline__ void buffer_store16(rsrc_t r, uint32_t offset, const uint4 &v) {
+    const u32x4 x = {v.x, v.y, v.z, v.w};
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, offset, 0, 0);
+}
+
+// Pointers into the constant address space: a load through one with a
+// wave-uniform address is a scalar load through the scalar cache.  Only for
+// memory that no kernel in flight writes.
+template <class T>
+__device__ __forceinline__ const T __attribute__((address_space(4))) *as_const(const T *p) {
+    return (const T __attribute__((address_space(4))) *)p;
+}
+
 }  // namespace dev
 }  // namespace aesgpu

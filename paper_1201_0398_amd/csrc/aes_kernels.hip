@@ -67,18 +67,12 @@ __device__ __forceinline__ uint64_t block_index(uint64_t base, int j, uint32_t v
     return base + tile_slot<kLaneMajor, BPL>(j) - voff;
 }
 
-// Buffer resources for the tile at virtual position base.  A raw buffer
-// access whose offset lies past the resource's range reads zero or writes
-// nothing (the hardware checks it), so every lane issues its loads and
-// stores without a branch, and the compiler can count them exactly when it
-// places the waits that let the next tile's loads overlap this tile's rounds.
-// The resource starts at the tile's first real block and covers the blocks
-// of the tile that exist; lanes before block 0 get offsets that wrap to
-// values far past any range.
-using rsrc_t = __amdgpu_buffer_rsrc_t;
-using u32x4 = uint32_t __attribute__((ext_vector_type(4)));
-constexpr int kRawBufferWord3 = 0x00020000;   // gfx9 raw buffer, 32-bit data format
-
+// Buffer resources for the tile at virtual position base, so that every lane
+// issues its loads and stores without a branch and the compiler can place
+// the waits that let the next tile's loads overlap this tile's rounds.  The
+// resource starts at the tile's first real block and covers the blocks of
+// the tile that exist; lanes before block 0 get offsets that wrap to values
+// far past any range.
 struct TileView {
     rsrc_t in, out;
     uint32_t shift;   // lanes before block 0 in this tile (first tile only)
@@ -89,10 +83,8 @@ __device__ __forceinline__ TileView tile_view(const uint4 *in, uint4 *out, uint6
     const uint64_t first = base >= voff ? base - voff : 0;
     const uint32_t shift = base >= voff ? 0u : voff;
     const uint64_t left = first < n_full ? n_full - first : 0;
-    const int range = int(16u * uint32_t(left < tile ? left : tile));
-    return {__builtin_amdgcn_make_buffer_rsrc(const_cast<uint4 *>(in + first), 0, range,
-                                              kRawBufferWord3),
-            __builtin_amdgcn_make_buffer_rsrc(out + first, 0, range, kRawBufferWord3), shift};
+    const uint32_t bytes = 16u * uint32_t(left < tile ? left : tile);
+    return {buffer_rsrc(in + first, bytes), buffer_rsrc(out + first, bytes), shift};
 }
 
 template <bool kLaneMajor, int BPL>
@@ -103,25 +95,12 @@ __device__ __forceinline__ uint32_t lane_offset(const TileView &v, int j) {
 template <bool kLaneMajor, int BPL>
 __device__ __forceinline__ void load_tile(uint4 (&v)[BPL], const TileView &t) {
 #pragma unroll
-    for (int j = 0; j < BPL; ++j) {
-        const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(
-            t.in, lane_offset<kLaneMajor, BPL>(t, j), 0, 0);
-        v[j] = make_uint4(x[0], x[1], x[2], x[3]);
-    }
+    for (int j = 0; j < BPL; ++j) v[j] = buffer_load16(t.in, lane_offset<kLaneMajor, BPL>(t, j));
 }
 
 template <bool kLaneMajor, int BPL>
 __device__ __forceinline__ void store_block(const TileView &t, int j, const uint4 &o) {
-    const u32x4 x = {o.x, o.y, o.z, o.w};
-    __builtin_amdgcn_raw_buffer_store_b128(x, t.out, lane_offset<kLaneMajor, BPL>(t, j), 0, 0);
-}
-
-// Pointers into the constant address space: a load through one with a
-// wave-uniform address is a scalar load through the scalar cache.  Only for
-// memory that no kernel in flight writes.
-template <class T>
-__device__ __forceinline__ const T __attribute__((address_space(4))) *as_const(const T *p) {
-    return (const T __attribute__((address_space(4))) *)p;
+    buffer_store16(t.out, lane_offset<kLaneMajor, BPL>(t, j), o);
 }
 
 // T_t[x] from the table copy in device memory, for an index that is the same
@@ -179,12 +158,10 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     // range and write nothing; they give the loop entry the same order, so
     // that wait does not also cover the last stores on every iteration.
     {
-        const rsrc_t none = __builtin_amdgcn_make_buffer_rsrc(p.out, 0, 0, kRawBufferWord3);
-        const u32x4 zero = {0u, 0u, 0u, 0u};
+        const rsrc_t none = buffer_rsrc(p.out, 0);
 #pragma unroll
         for (int j = 0; j < BPL; ++j)
-            __builtin_amdgcn_raw_buffer_store_b128(zero, none, lane_offset<kLM, BPL>(view, j), 0,
-                                                   0);
+            buffer_store16(none, lane_offset<kLM, BPL>(view, j), make_uint4(0, 0, 0, 0));
     }
     for (uint64_t base = uint64_t(blockIdx.x) * tile; base < v_end; base += stride) {
         uint32_t s[BPL][4];
