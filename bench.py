@@ -7,6 +7,11 @@ bytes.  ``value`` is payload GB/s over the step (3 GiB of payload per step,
 HIP events on the launch stream; the CPU oracle is timed on a bounded sample
 of the same workload on the host cores.
 
+Warm-up: W untimed steps, extended until --min-warmup-s (default 0.3 s) of
+back-to-back work has passed, since the GPU clock ramps up over tens of
+milliseconds of sustained load; the timed steps follow with no other GPU work
+in between.  The JSON line's "warmup" is the number of warm-up steps run.
+
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --copy-calibration   (plain 1 GiB device copies, for
                                              scaling HBM byte counters)
@@ -60,8 +65,11 @@ def log(msg: str) -> None:
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--min-warmup-s", type=float, default=0.3,
+                    help="keep warming up until this much wall time has passed (the GPU "
+                         "clock ramps up over tens of ms of sustained load)")
     ap.add_argument("--bytes", type=int, default=GIB)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-bytes", type=int, default=96 << 20)
@@ -266,13 +274,20 @@ def main() -> int:
             for i, n in enumerate(names):
                 events[n].append((ev[i], ev[i + 1]))
 
-    for _ in range(args.warmup):
-        step(False)
+    step(False)
     torch.cuda.synchronize()
     if not torch.equal(d_pt, d_in):
         raise SystemExit("round trip failed before timing")
-    log(f"timing {args.steps} steps")
+    # Warm-up runs straight into the timed region (no other GPU work between),
+    # W steps or longer, until min_warmup_s of back-to-back work has passed.
+    warm, t_w = 0, time.perf_counter()
+    while warm < args.warmup or time.perf_counter() - t_w < args.min_warmup_s:
+        step(False)
+        warm += 1
+        if warm % 8 == 0:
+            torch.cuda.synchronize()
     torch.cuda.synchronize()
+    log(f"warmed up with {warm} steps; timing {args.steps} steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(True)
@@ -290,7 +305,7 @@ def main() -> int:
                   for n in names}
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "steps": args.steps, "warmup": warm, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "AES-128 ECB encrypt + ECB decrypt + CTR (nonce||BE32, ctr0=1) of "
