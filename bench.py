@@ -114,6 +114,13 @@ def single_rates(torch, A, ctx, w, d_in, d_out, reps: int = 3) -> dict:
             torch, lambda: A.aesgpu_ecb_decrypt(ctx, k, d_in, d_out), reps)
         rates[(bits, "ctr")] = n / time_call(
             torch, lambda: A.aesgpu_ctr_xcrypt(ctx, k, w.nonce, 1, d_in, d_out), reps)
+        # The modes the paper adds: CBC decryption (Eq. (2)) and its CTR
+        # flavour with a 128-bit little-endian counter (IV + block index).
+        iv = bytes(w.nonce) + bytes(4)
+        rates[(bits, "cbc_dec")] = n / time_call(
+            torch, lambda: A.aesgpu_cbc_decrypt(ctx, k, iv, d_in, d_out), reps)
+        rates[(bits, "ctr_le128")] = n / time_call(
+            torch, lambda: A.aesgpu_ctr_le128_xcrypt(ctx, k, iv, 0, d_in, d_out), reps)
     return rates
 
 

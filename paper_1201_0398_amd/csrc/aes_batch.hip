@@ -168,7 +168,7 @@ __device__ __forceinline__ T load_uniform(const T *src) {
 __device__ __forceinline__ void counter_round1(const uint32_t *lds, const Bases &b,
                                                const CtrConsts &cc, uint32_t ctr,
                                                uint32_t (&s)[4]) {
-    const uint32_t w3 = bswap32(ctr) ^ cc.k03;
+    const uint32_t w3 = bswap32(ctr) ^ cc.kvar;
     s[0] = cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
     s[1] = cc.p[1] ^ tlook<2>(lds, w3, b.t[2]);
     s[2] = cc.p[2] ^ tlook<1>(lds, w3, b.t[1]);
@@ -201,7 +201,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
         uint32_t x[3];
 #pragma unroll
         for (int c = 0; c < 3; ++c) x[c] = m.nonce[c] ^ k0[c];
-        cc.k03 = k0[3];
+        cc.kvar = k0[3];
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
             uint32_t v = k1[c];

@@ -2,6 +2,7 @@
 // argument validation and the C ABI entry points for single buffers.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstring>
 
 #include "aes_internal.h"
@@ -98,6 +99,37 @@ int check_buffers(const aesgpu_ctx *ctx, const aesgpu_key *key, const void *in, 
                     : (partial_overlap(in, out, n_bytes) || in == out))
         return AESGPU_EINVAL;
     return AESGPU_OK;
+}
+
+// x (four little-endian words of a 128-bit integer) += v, modulo 2^128.
+void add128(uint32_t (&x)[4], uint64_t v) {
+    uint64_t carry = v;
+    for (int c = 0; c < 4 && carry; ++c) {
+        const uint64_t t = uint64_t(x[c]) + (carry & 0xFFFFFFFFull);
+        x[c] = uint32_t(t);
+        carry = (carry >> 32) + (t >> 32);
+    }
+}
+
+// Round-1 constants of a counter block whose word `var` varies and whose other
+// words are x[]: for output word c (Eq. (1) reads byte k of word (c + k) mod 4)
+// the XOR of the round-1 key word and the three table terms that do not read
+// word `var`.  x0 (the whitened fixed words) is passed through.
+CtrConsts ctr_consts(const aesgpu_key *key, const uint32_t (&x)[4], int var, CtrConsts cc) {
+    const HostTables &t = host_tables();
+    uint32_t s[4];
+    for (int c = 0; c < 4; ++c) s[c] = x[c] ^ key->enc[c];
+    cc.kvar = key->enc[var];
+    for (int c = 0; c < 4; ++c) {
+        uint32_t p = key->enc[4 + c];
+        for (int k = 0; k < 4; ++k) {
+            const int i = (c + k) & 3;
+            if (i == var) continue;
+            p ^= t.words[kTe + 256 * k + ((s[i] >> (8 * k)) & 0xFF)];
+        }
+        cc.p[c] = p;
+    }
+    return cc;
 }
 
 int run(aesgpu_ctx *ctx, const LaunchArgs &a, aesgpu_stream_t stream) {
@@ -256,22 +288,11 @@ int aesgpu_ctr_xcrypt(aesgpu_ctx *ctx, const aesgpu_key *key, const uint8_t *non
     a.rk = reinterpret_cast<const RoundKeys *>(key->enc);
     a.ctr0 = ctr0;
     // Round-1 constants: counter words 0..2 are the nonce for every block.
-    const HostTables &t = host_tables();
-    uint32_t x[3];
-    for (int c = 0; c < 3; ++c) x[c] = le32(nonce + 4 * c) ^ key->enc[c];
-    for (int c = 0; c < 3; ++c) a.ctr.x0[c] = x[c];
-    a.ctr.k03 = key->enc[3];
-    for (int c = 0; c < 4; ++c) {
-        // Output word c of round 1 reads byte k of word (c + k) mod 4; the
-        // term with (c + k) mod 4 == 3 depends on the block and is left out.
-        uint32_t p = key->enc[4 + c];
-        for (int k = 0; k < 4; ++k) {
-            const int i = (c + k) & 3;
-            if (i == 3) continue;
-            p ^= t.words[kTe + 256 * k + ((x[i] >> (8 * k)) & 0xFF)];
-        }
-        a.ctr.p[c] = p;
-    }
+    uint32_t x[4];
+    for (int c = 0; c < 3; ++c) x[c] = le32(nonce + 4 * c);
+    x[3] = 0;
+    for (int c = 0; c < 3; ++c) a.ctr.x0[c] = x[c] ^ key->enc[c];
+    a.ctr = ctr_consts(key, x, 3, a.ctr);
     return run(ctx, a, stream);
 }
 
@@ -281,16 +302,32 @@ int aesgpu_ctr_le128_xcrypt(aesgpu_ctx *ctx, const aesgpu_key *key, const uint8_
     if (!ctx || !key_ok(key) || !iv) return AESGPU_EINVAL;
     int st = check_buffers(ctx, key, d_in, d_out, n_bytes, true);
     if (st != AESGPU_OK || n_bytes == 0) return st;
-    LaunchArgs a{};
-    a.op = Op::kCtrLe128;
-    a.nr = key->nr;
-    a.in = d_in;
-    a.out = d_out;
-    a.n_bytes = n_bytes;
-    a.rk = reinterpret_cast<const RoundKeys *>(key->enc);
-    for (int c = 0; c < 4; ++c) a.iv[c] = le32(iv + 4 * c);
-    a.index0 = index0;
-    return run(ctx, a, stream);
+    // Counter words 1..3 are folded into round-1 constants, so a launch must
+    // not carry out of word 0: the call is split where word 0 wraps (at most
+    // once per 2^32 blocks).
+    const uint64_t n_blocks = (uint64_t(n_bytes) + 15) / 16;
+    uint32_t x[4];
+    for (int c = 0; c < 4; ++c) x[c] = le32(iv + 4 * c);
+    add128(x, index0);
+    for (uint64_t done = 0; done < n_blocks;) {
+        const uint64_t room = (1ull << 32) - x[0];
+        const uint64_t seg = std::min<uint64_t>(n_blocks - done, room);
+        LaunchArgs a{};
+        a.op = Op::kCtrLe128;
+        a.nr = key->nr;
+        a.in = static_cast<const uint8_t *>(d_in) + 16 * done;
+        a.out = static_cast<uint8_t *>(d_out) + 16 * done;
+        a.n_bytes = std::min<uint64_t>(16 * seg, uint64_t(n_bytes) - 16 * done);
+        a.rk = reinterpret_cast<const RoundKeys *>(key->enc);
+        for (int c = 0; c < 4; ++c) a.iv[c] = x[c];
+        a.index0 = 0;
+        a.ctr = ctr_consts(key, x, 0, a.ctr);
+        st = run(ctx, a, stream);
+        if (st != AESGPU_OK) return st;
+        done += seg;
+        add128(x, seg);
+    }
+    return AESGPU_OK;
 }
 
 int aesgpu_cbc_decrypt(aesgpu_ctx *ctx, const aesgpu_key *key, const uint8_t *iv,

@@ -26,12 +26,14 @@ struct alignas(16) RoundKeys {
     uint32_t w[60];
 };
 
-// First-round constants of CTR mode.  With counter words 0..2 fixed by the
-// nonce, every output word of round 1 is one table lookup on counter word 3
-// XORed with a constant that depends only on the key and the nonce.
+// First-round constants of the CTR modes.  Three of the four counter words
+// are fixed over a launch (the nonce for the 32-bit big-endian counter, words
+// 1..3 of the 128-bit little-endian counter, which the host keeps fixed by
+// splitting a call where word 0 wraps), so every output word of round 1 is one
+// table lookup on the varying word XORed with a constant of key and counter.
 struct alignas(16) CtrConsts {
-    uint32_t x0[3];   // counter words 0..2 after the initial AddRoundKey
-    uint32_t k03;     // initial round key word 3
+    uint32_t x0[3];   // BE32: counter words 0..2 after the initial AddRoundKey
+    uint32_t kvar;    // initial round key word of the varying counter word (3 or 0)
     uint32_t p[4];    // round-1 constants, one per output word
 };
 
@@ -56,10 +58,10 @@ struct LaunchArgs {
     void *out;
     uint64_t n_bytes;     // ECB/CBC: 16 * n_blocks
     const RoundKeys *rk;  // enc keys for encryption/CTR, dec keys for decryption
-    CtrConsts ctr;        // kCtrBe32 only
+    CtrConsts ctr;        // kCtrBe32, kCtrLe128
     uint32_t ctr0;        // kCtrBe32 only
-    uint32_t iv[4];       // kCtrLe128 (IV words), kCbcDec (IV words)
-    uint64_t index0;      // kCtrLe128
+    uint32_t iv[4];       // kCtrLe128 (counter of block 0), kCbcDec (IV words)
+    uint64_t index0;      // kCtrLe128: added to iv (0 from the host's own calls)
 };
 
 // Enqueues the kernel for `a` on `stream`; returns an AESGPU status.

@@ -46,6 +46,7 @@ struct Params {
     uint32_t ctr0;
     const uint32_t *tables;
     uint64_t index0;        // LE-128 counter offset
+    uint32_t ctr_y;         // LE-128: word 0 of the counter of virtual slot 0
     uint32_t voff;          // virtual index = block index + voff (CTR: ctr0 mod 64 * BPL)
     uint32_t iv[4];
     CtrConsts cc;
@@ -103,6 +104,20 @@ __device__ __forceinline__ void store_block(const TileView &t, int j, const uint
     buffer_store16(t.out, lane_offset<kLaneMajor, BPL>(t, j), o);
 }
 
+// CBC (lane-major tiles): block first - 1, where first is the wave's first
+// block in the tile at base (the same address in every lane), read through a
+// resource that starts one block before the tile; zero where first == 0 (the
+// caller substitutes the IV) or past the end.
+template <int BPL>
+__device__ __forceinline__ uint4 load_wave_prev(const uint4 *in, uint64_t base, uint32_t wave_first,
+                                                uint64_t n_full, uint32_t tile) {
+    const uint64_t start = base > 0 ? base - 1 : 0;
+    const uint32_t shift = base > 0 ? 0u : 1u;
+    const uint64_t left = start < n_full ? n_full - start : 0;
+    const rsrc_t r = buffer_rsrc(in + start, 16u * uint32_t(left < tile + 1u ? left : tile + 1u));
+    return buffer_load16(r, (wave_first * BPL - shift) * 16u);
+}
+
 // T_t[x] from the table copy in device memory, for an index that is the same
 // in every lane: one scalar load instead of an LDS instruction.
 __device__ __forceinline__ uint32_t tab_u(const uint32_t *te, uint32_t t, uint32_t x) {
@@ -119,7 +134,7 @@ __device__ __forceinline__ void counter_state(const Params &p, uint64_t idx, uin
         s[0] = p.cc.x0[0];
         s[1] = p.cc.x0[1];
         s[2] = p.cc.x0[2];
-        s[3] = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.k03;
+        s[3] = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.kvar;
     } else {
         // IV + index0 + idx as a 128-bit little-endian integer
         const uint64_t add = p.index0 + idx;
@@ -138,7 +153,7 @@ template <Op OP, int NR, int BPL>
 __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
     constexpr bool kCtr = (OP == Op::kCtrBe32 || OP == Op::kCtrLe128);
-    constexpr bool kLM = (OP == Op::kCtrBe32);   // lane-major tiles
+    constexpr bool kLM = kCtr || OP == Op::kCbcDec;   // lane-major tiles
     __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords];
     stage_tables<kInv>(lds, p.tables);
     const Bases b = lane_bases();
@@ -151,8 +166,12 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     // The blocks of the next tile are loaded while the current one is
     // computed, so HBM latency overlaps the rounds even at low occupancy.
     uint4 next[BPL];
+    uint4 next_prev = make_uint4(0, 0, 0, 0);   // CBC only
     TileView view = tile_view(p.in, p.out, uint64_t(blockIdx.x) * tile, p.n_full, p.voff, tile);
     load_tile<kLM, BPL>(next, view);
+    if constexpr (OP == Op::kCbcDec)
+        next_prev = load_wave_prev<BPL>(p.in, uint64_t(blockIdx.x) * tile, wave_first, p.n_full,
+                                        uint32_t(tile));
     // In the loop a tile's loads are followed by the previous tile's stores,
     // and the loop top waits for the loads only.  These stores have an empty
     // range and write nothing; they give the loop entry the same order, so
@@ -168,24 +187,46 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         uint4 in[BPL];
 #pragma unroll
         for (int j = 0; j < BPL; ++j) in[j] = next[j];
+        const uint4 wave_prev = next_prev;
         const TileView cur = view;
         view = tile_view(p.in, p.out, base + stride, p.n_full, p.voff, tile);
         load_tile<kLM, BPL>(next, view);
-        // CTR rounds 1 and 2.  Round 1: output word c needs one lookup, on
-        // byte (3 - c) of counter word 3; the other three terms are
-        // constants.  The wave's counters share all but their low byte, so
-        // bytes 0..2 of word 3 and round-1 words 1..3 are wave-uniform
-        // (scalar); only word 0 differs per block.  Round 2 (Eq. (1) with
-        // round key 2): each output word has one term on word 0 (per block)
-        // and three on words 1..3 (uniform).
-        uint32_t c[4] = {0, 0, 0, 0};
-        if constexpr (OP == Op::kCtrBe32) {
-            const uint32_t ctr_first = p.ctr0 - p.voff + uint32_t(base) + wave_first * BPL;
-            const uint32_t w3u = bswap32(ctr_first) ^ p.cc.k03;
+        if constexpr (OP == Op::kCbcDec)
+            next_prev = load_wave_prev<BPL>(p.in, base + stride, wave_first, p.n_full,
+                                            uint32_t(tile));
+        // CTR rounds 1 and 2.  The wave's 64 * BPL counters start at a
+        // multiple of 64 * BPL, so they differ only in their low byte, and so
+        // does the whitened counter block.  Round 1 (Eq. (1)): the varying
+        // byte feeds one table term of output word 0; the other 15 terms and
+        // output words 1..3 are wave-uniform.  Round 2: each output word has
+        // one term on word 0 (per block) and three on words 1..3 (uniform).
+        // The uniform lookups are scalar loads, once per wave and tile.
+        uint32_t c[4] = {0, 0, 0, 0};   // round-2 uniform part, per output word
+        uint32_t r1 = 0;                // round-1 uniform part of word 0
+        uint32_t y0 = 0;                // LE-128: counter word 0 of the wave's first slot
+        if constexpr (kCtr) {
             const uint32_t *te = p.tables + kTe;
-            const uint32_t u1 = p.cc.p[1] ^ tab_u(te, 2, byte_of(w3u, 2));
-            const uint32_t u2 = p.cc.p[2] ^ tab_u(te, 1, byte_of(w3u, 1));
-            const uint32_t u3 = p.cc.p[3] ^ tab_u(te, 0, byte_of(w3u, 0));
+            uint32_t u1, u2, u3;        // round-1 output words 1..3
+            if constexpr (OP == Op::kCtrBe32) {
+                // Counter block: nonce words 0..2 (folded into cc.p by the
+                // host), word 3 = BE32(counter), whose byte 3 varies.
+                const uint32_t ctr_first = p.ctr0 - p.voff + uint32_t(base) + wave_first * BPL;
+                const uint32_t w3u = bswap32(ctr_first) ^ p.cc.kvar;
+                r1 = p.cc.p[0];
+                u1 = p.cc.p[1] ^ tab_u(te, 2, byte_of(w3u, 2));
+                u2 = p.cc.p[2] ^ tab_u(te, 1, byte_of(w3u, 1));
+                u3 = p.cc.p[3] ^ tab_u(te, 0, byte_of(w3u, 0));
+            } else {
+                // Counter block: the 128-bit LE integer whose words 1..3 are
+                // fixed over the launch (folded into cc.p by the host) and
+                // whose word 0 is ctr_y + slot; its byte 0 varies.
+                y0 = p.ctr_y + uint32_t(base) + wave_first * BPL;
+                const uint32_t s0u = y0 ^ p.cc.kvar;
+                r1 = p.cc.p[0];
+                u1 = p.cc.p[1] ^ tab_u(te, 3, byte_of(s0u, 3));
+                u2 = p.cc.p[2] ^ tab_u(te, 2, byte_of(s0u, 2));
+                u3 = p.cc.p[3] ^ tab_u(te, 1, byte_of(s0u, 1));
+            }
             const uint32_t *k2 = &p.rk.w[8];
             c[0] = tab_u(te, 1, byte_of(u1, 1)) ^ tab_u(te, 2, byte_of(u2, 2)) ^
                    tab_u(te, 3, byte_of(u3, 3)) ^ k2[0];
@@ -204,18 +245,23 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 s[j][1] = in[j].y ^ p.rk.w[1];
                 s[j][2] = in[j].z ^ p.rk.w[2];
                 s[j][3] = in[j].w ^ p.rk.w[3];
-            } else if constexpr (OP == Op::kCtrBe32) {
-                const uint32_t w3 = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.k03;
-                const uint32_t v0 = p.cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
+            } else {
+                // Round-1 word 0: the one per-block lookup of round 1.
+                uint32_t v0;
+                if constexpr (OP == Op::kCtrBe32) {
+                    const uint32_t w3 = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.kvar;
+                    v0 = r1 ^ tlook<3>(lds, w3, b.t[3]);
+                } else {
+                    const uint32_t w0 = (y0 | tile_slot<true, BPL>(j) % (64u * BPL)) ^ p.cc.kvar;
+                    v0 = r1 ^ tlook<0>(lds, w0, b.t[0]);
+                }
                 s[j][0] = tlook<0>(lds, v0, b.t[0]) ^ c[0];
                 s[j][1] = tlook<3>(lds, v0, b.t[3]) ^ c[1];
                 s[j][2] = tlook<2>(lds, v0, b.t[2]) ^ c[2];
                 s[j][3] = tlook<1>(lds, v0, b.t[1]) ^ c[3];
-            } else {
-                counter_state<OP>(p, idx, s[j]);
             }
         }
-        const int first = (OP == Op::kCtrBe32) ? 3 : 1;
+        const int first = kCtr ? 3 : 1;
 #pragma unroll
         for (int r = 1; r < NR; ++r) {
             if (r < first) continue;
@@ -238,20 +284,27 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 o.z ^= in[j].z;
                 o.w ^= in[j].w;
             } else if constexpr (OP == Op::kCbcDec) {
-                // Eq. (2): XOR with the previous ciphertext block.  Lane L > 0
-                // of a wave takes it from lane L - 1 (a DPP shift of the
-                // wave); lane 0's comes from the IV or a scalar load.
-                const uint64_t first_idx = base + uint64_t(j) * kWG + wave_first;
-                uint4 prev0 = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
-                if (first_idx > 0) {
-                    const uint64_t q = first_idx - 1 < p.n_full ? first_idx - 1 : p.n_full - 1;
-                    const auto *w = as_const(reinterpret_cast<const uint32_t *>(p.in + q));
-                    prev0 = make_uint4(w[0], w[1], w[2], w[3]);
+                // Eq. (2): XOR with the previous ciphertext block.  Slot j > 0
+                // takes the lane's own slot j - 1; slot 0 takes the last slot
+                // of lane L - 1 (a DPP shift of the wave), and lane 0 the
+                // block loaded with the tile (the IV for block 0).
+                uint4 q;
+                if (j > 0) {
+                    q = in[j - 1];
+                } else {
+                    const uint4 prev0 = base + wave_first * BPL == 0
+                                            ? make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3])
+                                            : wave_prev;
+                    const uint4 &l = in[BPL - 1];
+                    q.x = __builtin_amdgcn_update_dpp(prev0.x, l.x, 0x138, 0xf, 0xf, false);
+                    q.y = __builtin_amdgcn_update_dpp(prev0.y, l.y, 0x138, 0xf, 0xf, false);
+                    q.z = __builtin_amdgcn_update_dpp(prev0.z, l.z, 0x138, 0xf, 0xf, false);
+                    q.w = __builtin_amdgcn_update_dpp(prev0.w, l.w, 0x138, 0xf, 0xf, false);
                 }
-                o.x ^= __builtin_amdgcn_update_dpp(prev0.x, in[j].x, 0x138, 0xf, 0xf, false);
-                o.y ^= __builtin_amdgcn_update_dpp(prev0.y, in[j].y, 0x138, 0xf, 0xf, false);
-                o.z ^= __builtin_amdgcn_update_dpp(prev0.z, in[j].z, 0x138, 0xf, 0xf, false);
-                o.w ^= __builtin_amdgcn_update_dpp(prev0.w, in[j].w, 0x138, 0xf, 0xf, false);
+                o.x ^= q.x;
+                o.y ^= q.y;
+                o.z ^= q.z;
+                o.w ^= q.w;
             }
             store_block<kLM, BPL>(cur, j, o);
         }
@@ -279,8 +332,18 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
 template <Op OP, int NR, int BPL>
 int launch_one(Params p, int n_cu, hipStream_t stream) {
     // CTR: shift the mapping so every wave's 64 * BPL counters start at a
-    // multiple of 64 * BPL.
-    p.voff = OP == Op::kCtrBe32 ? (p.ctr0 & (64u * BPL - 1u)) : 0u;
+    // multiple of 64 * BPL (so they differ only in their low byte).
+    if constexpr (OP == Op::kCtrBe32) {
+        p.voff = p.ctr0 & (64u * BPL - 1u);
+    } else if constexpr (OP == Op::kCtrLe128) {
+        // Word 0 of the counter of block 0 is iv[0] + index0 (words 1..3 are
+        // fixed over the launch; the host splits calls where word 0 wraps).
+        const uint32_t x0 = p.iv[0] + uint32_t(p.index0);
+        p.voff = x0 & (64u * BPL - 1u);
+        p.ctr_y = x0 - p.voff;
+    } else {
+        p.voff = 0;
+    }
     // At least one workgroup: a CTR call shorter than a block has only a tail.
     const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
     const uint64_t tiles = (v_end + uint64_t(kWG) * BPL - 1) / (uint64_t(kWG) * BPL);

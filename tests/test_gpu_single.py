@@ -199,6 +199,28 @@ def test_ctr_le128_matches_oracle(A, ctx, kb):
             assert np.array_equal(from_dev(d_out), oracle.ctr_le128(key, iv, index0, data))
 
 
+def test_ctr_le128_alignment_and_short(A, ctx):
+    """Counter starts at every residue the lane mapping shifts by (IV + index0
+    modulo 256), runs shorter than a wave's 256 counters, and a start 3 blocks
+    below a carry out of every 32-bit word."""
+    import torch
+    rng = np.random.default_rng(4100)
+    key = rng.integers(0, 256, 16, dtype=np.uint8)
+    k = A.aesgpu_expand_key(key)
+    base = rng.integers(0, 256, 16, dtype=np.uint8)
+    top = np.frombuffer(((1 << 128) - 3).to_bytes(16, "little"), dtype=np.uint8)
+    for iv, index0 in [(base, 0), (base, 1), (base, 255), (base, 256 + 77), (top, 0), (top, 2)]:
+        for n_bytes in [1, 16 * 63 + 5, 16 * 255, 16 * 257 + 1, 16 * (2 * TILE + 9)]:
+            log(f"case: CTR-LE128 index0={index0} n_bytes={n_bytes}")
+            data = rng.integers(0, 256, n_bytes, dtype=np.uint8)
+            d_in = to_dev(data)
+            d_out = torch.full((n_bytes + 64,), 0x5A, dtype=torch.uint8, device="cuda")
+            A.aesgpu_ctr_le128_xcrypt(ctx, k, iv, index0, d_in, d_out, n_bytes)
+            out = from_dev(d_out)
+            assert np.array_equal(out[:n_bytes], oracle.ctr_le128(key, iv, index0, data))
+            assert (out[n_bytes:] == 0x5A).all(), "wrote past the end"
+
+
 @pytest.mark.parametrize("kb", [16, 24, 32])
 def test_cbc_decrypt_matches_oracle(A, ctx, kb):
     import torch
