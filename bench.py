@@ -77,6 +77,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100000)
     return ap.parse_args()
 
@@ -212,6 +213,64 @@ def serving_bench(torch, A, ctx, n_requests: int) -> dict:
                         "device-resident; latency = completion seen by the host - arrival"}
 
 
+def pipeline_bench(torch, A, ctx, key_bytes: bytes) -> dict:
+    """Host buffers in and out (the paper's upload / draw / read-back path):
+    AES-128 ECB encryption through the chunked host-staged pipeline, wall time
+    per call including both PCIe transfers, for pinned buffers over a range of
+    sizes and for pageable buffers at 1 GiB; the plain pinned copy rates in
+    each direction give the link's own bound."""
+    import numpy as np
+    k = A.aesgpu_expand_key(key_bytes)
+    op = A.make_host_op(A.AESGPU_OP_ECB_ENCRYPT)
+    top = 1 << 30
+    a_in, h_in = A.aesgpu_host_alloc(top)
+    a_out, h_out = A.aesgpu_host_alloc(top)
+    rng = np.random.default_rng(5)
+    h_in[:] = np.frombuffer(rng.bytes(top), dtype=np.uint8)
+    out = {"op": "AES-128 ECB encrypt, host buffer in and out", "chunk_bytes": 8 << 20,
+           "slots": 3}
+    try:
+        pl = A.aesgpu_pipeline_create(ctx, 8 << 20, 3)
+        pl_dma = A.aesgpu_pipeline_create(ctx, 8 << 20, 3, A.AESGPU_PIPELINE_COPY)
+
+        def wall(fn, n_bytes):
+            reps = max(3, min(200, (256 << 20) // n_bytes))
+            fn()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                fn()
+                ts.append(time.perf_counter() - t0)
+            return float(np.median(ts))
+
+        for name, p in (("pinned_zero_copy", pl), ("pinned_dma_chunks", pl_dma)):
+            rows = []
+            for n in [1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 24, 1 << 26, 1 << 28, 1 << 30]:
+                t = wall(lambda: A.aesgpu_pipeline_run(p, k, op, a_in, a_out, n), n)
+                rows.append({"bytes": n, "us": round(t * 1e6, 1), "GB_s": round(n / t / 1e9, 2)})
+                log(f"pipeline {name} {n} B: {rows[-1]}")
+            out[name] = rows
+        A.aesgpu_pipeline_destroy(pl_dma)
+        src = np.asarray(h_in).copy()
+        dst = np.empty_like(src)
+        t = wall(lambda: A.aesgpu_pipeline_run(pl, k, op, src, dst, top), top)
+        out["pageable_1GiB_GB_s"] = round(top / t / 1e9, 2)
+        del src, dst
+        A.aesgpu_pipeline_destroy(pl)
+        # The link alone: pinned 1 GiB copies each way (torch's own copies).
+        dev = torch.empty(top, dtype=torch.uint8, device="cuda")
+        hb = torch.empty(top, dtype=torch.uint8, pin_memory=True)
+        t_h2d = wall(lambda: (dev.copy_(hb, non_blocking=True), torch.cuda.synchronize()), top)
+        t_d2h = wall(lambda: (hb.copy_(dev, non_blocking=True), torch.cuda.synchronize()), top)
+        out["pcie_h2d_GB_s"] = round(top / t_h2d / 1e9, 2)
+        out["pcie_d2h_GB_s"] = round(top / t_d2h / 1e9, 2)
+        del dev, hb
+    finally:
+        A.aesgpu_host_free(a_in)
+        A.aesgpu_host_free(a_out)
+    return out
+
+
 def cpu_baseline(sample_bytes: int) -> dict:
     import numpy as np
 
@@ -334,6 +393,8 @@ def main() -> int:
         out["batched"] = batched_bench(torch, A, ctx, rates, args.batched_reps)
     if not args.no_serving:
         out["serving"] = serving_bench(torch, A, ctx, args.serve_requests)
+    if not args.no_pipeline:
+        out["host_pipeline"] = pipeline_bench(torch, A, ctx, key)
     A.aesgpu_destroy(ctx)
     del d_in, d_ct
     if not args.no_cpu_baseline:

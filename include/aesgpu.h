@@ -227,6 +227,71 @@ int aesgpu_batch_info(const aesgpu_batch *plan, aesgpu_batch_stats *out);
 void aesgpu_batch_free(aesgpu_batch *plan);
 
 /* ------------------------------------------------------------------------ */
+/* Host-staged pipeline: host buffers in, host buffers out                   */
+/* ------------------------------------------------------------------------ */
+
+/*
+ * Pinned host memory, mapped into the device's address space, that
+ * aesgpu_pipeline_run() recognises (no staging copy).  *out receives the host
+ * pointer.  Errors: EINVAL (out NULL, zero size), ENOMEM, EHIP.
+ * aesgpu_host_free() takes only pointers returned here (EINVAL otherwise;
+ * NULL is ignored).
+ */
+int aesgpu_host_alloc(size_t n_bytes, void **out);
+int aesgpu_host_free(void *p);
+
+enum {
+    AESGPU_OP_ECB_ENCRYPT = 0,
+    AESGPU_OP_ECB_DECRYPT = 1,
+    AESGPU_OP_CTR = 2,          /* nonce || BE32(ctr0 + i), as aesgpu_ctr_xcrypt() */
+    AESGPU_OP_CTR_LE128 = 3,    /* iv + i as a 128-bit LE integer, as aesgpu_ctr_le128_xcrypt() */
+    AESGPU_OP_CBC_DECRYPT = 4   /* Eq. (2) with iv, as aesgpu_cbc_decrypt() */
+};
+
+/* One mode call over a host buffer (host struct). */
+typedef struct {
+    uint32_t op;        /* AESGPU_OP_* */
+    uint32_t ctr0;      /* AESGPU_OP_CTR */
+    uint8_t nonce[12];  /* AESGPU_OP_CTR */
+    uint8_t iv[16];     /* AESGPU_OP_CTR_LE128, AESGPU_OP_CBC_DECRYPT */
+} aesgpu_host_op;
+
+typedef struct aesgpu_pipeline aesgpu_pipeline;
+
+#define AESGPU_PIPELINE_COPY 1u /* move aesgpu_host_alloc() memory by DMA copies, not zero copy */
+
+/*
+ * The data path of the paper's section 3 (upload, encrypt, read back), as a
+ * pipeline: chunk_bytes (a multiple of 16; 0 = 8 MiB) per chunk and n_slots
+ * chunks in flight (1..16; 0 = 3), each slot with its own stream, two device
+ * chunk buffers and two pinned staging buffers, allocated here.  flags: 0 or
+ * AESGPU_PIPELINE_COPY.  Errors: EINVAL, ENOMEM, EHIP.
+ */
+int aesgpu_pipeline_create(aesgpu_ctx *ctx, size_t chunk_bytes, int n_slots, uint32_t flags,
+                           aesgpu_pipeline **out);
+
+/*
+ * Runs `op` over n_bytes from host memory h_in to host memory h_out and
+ * returns when the output is complete.  When both ranges lie in
+ * aesgpu_host_alloc() allocations (and AESGPU_PIPELINE_COPY is not set), the
+ * library's kernel for `op` reads and writes them directly over the host link
+ * (zero copy, both directions at once).  Otherwise each chunk is copied to
+ * the device, processed (chunk k continues the counter or the CBC chain of
+ * chunk k - 1) and copied back, on its slot's stream, so transfers overlap
+ * kernels; aesgpu_host_alloc() memory is then moved by DMA and other memory
+ * through the pinned staging buffers (a CPU copy per chunk).
+ * h_in == h_out runs in place (not for CBC); other overlap is EINVAL.  ECB
+ * and CBC take whole blocks.  Calls on one pipeline must not overlap in time.
+ * Errors: EINVAL, ECTR_OVERFLOW, EHIP.
+ */
+int aesgpu_pipeline_run(aesgpu_pipeline *pl, const aesgpu_key *key, const aesgpu_host_op *op,
+                        const void *h_in, void *h_out, size_t n_bytes);
+
+/* Frees the pipeline's buffers and streams (waits for its work).  NULL is
+ * ignored. */
+void aesgpu_pipeline_destroy(aesgpu_pipeline *pl);
+
+/* ------------------------------------------------------------------------ */
 /* Device-memory range allocator (host bookkeeping only)                    */
 /* ------------------------------------------------------------------------ */
 

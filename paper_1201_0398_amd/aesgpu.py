@@ -89,6 +89,18 @@ class aesgpu_request(ctypes.Structure):
                 ("key_id", ctypes.c_uint32), ("dir", ctypes.c_uint32)]
 
 
+AESGPU_OP_ECB_ENCRYPT = 0
+AESGPU_OP_ECB_DECRYPT = 1
+AESGPU_OP_CTR = 2
+AESGPU_OP_CTR_LE128 = 3
+AESGPU_OP_CBC_DECRYPT = 4
+
+
+class aesgpu_host_op(ctypes.Structure):
+    _fields_ = [("op", ctypes.c_uint32), ("ctr0", ctypes.c_uint32),
+                ("nonce", ctypes.c_uint8 * 12), ("iv", ctypes.c_uint8 * 16)]
+
+
 class aesgpu_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("batches", "requests_submitted", "requests_done", "bytes_done",
@@ -138,6 +150,11 @@ def _load() -> ctypes.CDLL:
         "aesgpu_server_replay": ([vp, ctypes.POINTER(aesgpu_request), sz, ctypes.c_double,
                                   ctypes.POINTER(aesgpu_done)], ci),
         "aesgpu_server_destroy": ([vp], None),
+        "aesgpu_host_alloc": ([sz, ctypes.POINTER(vp)], ci),
+        "aesgpu_host_free": ([vp], ci),
+        "aesgpu_pipeline_create": ([vp, sz, ci, ctypes.c_uint32, ctypes.POINTER(vp)], ci),
+        "aesgpu_pipeline_run": ([vp, kp, ctypes.POINTER(aesgpu_host_op), vp, vp, sz], ci),
+        "aesgpu_pipeline_destroy": ([vp], None),
         "aesgpu_strerror": ([ci], ctypes.c_char_p),
         "aesgpu_ctx_num_cus": ([vp], ci),
     }
@@ -449,3 +466,65 @@ def make_requests(t_arrival, d_in, n_bytes, key_id, dir):
 
 def aesgpu_server_destroy(server) -> None:
     _lib.aesgpu_server_destroy(server)
+
+
+# ---- host-staged pipeline ----------------------------------------------------
+
+def aesgpu_host_alloc(n_bytes: int):
+    """Pinned host memory; returns (address, numpy uint8 view of n_bytes)."""
+    import numpy as np
+    p = ctypes.c_void_p()
+    _check(_lib.aesgpu_host_alloc(n_bytes, ctypes.byref(p)), "aesgpu_host_alloc")
+    view = np.ctypeslib.as_array((ctypes.c_uint8 * n_bytes).from_address(p.value))
+    return p.value, view
+
+
+def aesgpu_host_free(addr: int, check: bool = True) -> int:
+    st = _lib.aesgpu_host_free(addr)
+    return _check(st, "aesgpu_host_free") if check else st
+
+
+def _host_ptr(x) -> int | None:
+    """Host address of a contiguous numpy array (or an integer address)."""
+    if x is None or isinstance(x, int):
+        return x
+    import numpy as np
+    if isinstance(x, np.ndarray):
+        if not x.flags["C_CONTIGUOUS"]:
+            raise ValueError("host buffer must be contiguous")
+        return x.ctypes.data
+    raise TypeError(f"expected a numpy array or an address, got {type(x)}")
+
+
+def make_host_op(op: int, ctr0: int = 0, nonce=None, iv=None) -> aesgpu_host_op:
+    o = aesgpu_host_op()
+    o.op = op
+    o.ctr0 = ctr0
+    if nonce is not None:
+        o.nonce[:] = bytes(nonce)
+    if iv is not None:
+        o.iv[:] = bytes(iv)
+    return o
+
+
+AESGPU_PIPELINE_COPY = 1
+
+
+def aesgpu_pipeline_create(ctx, chunk_bytes: int = 0, n_slots: int = 0, flags: int = 0):
+    out = ctypes.c_void_p()
+    _check(_lib.aesgpu_pipeline_create(ctx, chunk_bytes, n_slots, flags, ctypes.byref(out)),
+           "aesgpu_pipeline_create")
+    return out
+
+
+def aesgpu_pipeline_run(pl, key: aesgpu_key, op: aesgpu_host_op, h_in, h_out,
+                        n_bytes: int | None = None, check: bool = True) -> int:
+    if n_bytes is None:
+        n_bytes = h_in.nbytes
+    st = _lib.aesgpu_pipeline_run(pl, ctypes.byref(key), ctypes.byref(op), _host_ptr(h_in),
+                                  _host_ptr(h_out), n_bytes)
+    return _check(st, "aesgpu_pipeline_run") if check else st
+
+
+def aesgpu_pipeline_destroy(pl) -> None:
+    _lib.aesgpu_pipeline_destroy(pl)

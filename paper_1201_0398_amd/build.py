@@ -13,7 +13,7 @@ LIB = os.path.join(PKG, "libaesgpu.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["aes_host.cpp", "aes_kernels.hip", "aes_batch.hip", "aes_server.cpp"]
+SOURCES = ["aes_host.cpp", "aes_kernels.hip", "aes_batch.hip", "aes_server.cpp", "aes_pipeline.cpp"]
 
 # Packed FP32 instructions are turned off for all device code.
 HIP_FLAGS = ["-O3", f"--offload-arch={ARCH}", "-std=c++17", "-fPIC", "-Wall",

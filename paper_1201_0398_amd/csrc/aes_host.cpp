@@ -82,11 +82,6 @@ bool partial_overlap(const void *a, const void *b, uint64_t n) {
     return x < y ? (y - x) < n : (x - y) < n;
 }
 
-bool key_ok(const aesgpu_key *k) {
-    return k && ((k->key_bits == 128 && k->nr == 10) || (k->key_bits == 192 && k->nr == 12) ||
-                 (k->key_bits == 256 && k->nr == 14));
-}
-
 // Common checks of a buffer call, in argument order.
 int check_buffers(const aesgpu_ctx *ctx, const aesgpu_key *key, const void *in, const void *out,
                   uint64_t n_bytes, bool in_place_ok) {
@@ -139,6 +134,11 @@ int run(aesgpu_ctx *ctx, const LaunchArgs &a, aesgpu_stream_t stream) {
 }
 
 }  // namespace
+
+bool key_ok(const aesgpu_key *k) {
+    return k && ((k->key_bits == 128 && k->nr == 10) || (k->key_bits == 192 && k->nr == 12) ||
+                 (k->key_bits == 256 && k->nr == 14));
+}
 
 const HostTables &host_tables() {
     static const HostTables t = build_tables();

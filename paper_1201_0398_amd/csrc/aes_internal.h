@@ -46,6 +46,9 @@ struct HostTables {
 // Builds the table image from the library's own GF(2^8) arithmetic.
 const HostTables &host_tables();
 
+// An expanded key with a consistent size and round count.
+bool key_ok(const aesgpu_key *k);
+
 // InvMixColumns of one little-endian column word (host).
 uint32_t inv_mix_column(uint32_t w);
 

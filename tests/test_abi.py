@@ -93,6 +93,15 @@ def test_calls_reject_null_context_before_any_hip_call(A):
     assert L.aesgpu_ctr_xcrypt(None, kp, nonce, 1, 16, 16, 16, None) == A.AESGPU_EINVAL
     assert L.aesgpu_ctr_le128_xcrypt(None, kp, nonce, 0, 16, 16, 16, None) == A.AESGPU_EINVAL
     assert L.aesgpu_cbc_decrypt(None, kp, nonce, 16, 32, 1, None) == A.AESGPU_EINVAL
+    out = ctypes.c_void_p()
+    assert L.aesgpu_pipeline_create(None, 0, 0, 0, ctypes.byref(out)) == A.AESGPU_EINVAL
+    assert out.value is None
+    op = A.make_host_op(A.AESGPU_OP_ECB_ENCRYPT)
+    assert L.aesgpu_pipeline_run(None, kp, ctypes.byref(op), 16, 32, 16) == A.AESGPU_EINVAL
+    assert L.aesgpu_host_alloc(0, ctypes.byref(out)) == A.AESGPU_EINVAL
+    assert L.aesgpu_host_free(4096) == A.AESGPU_EINVAL     # not from aesgpu_host_alloc
+    assert L.aesgpu_host_free(None) == A.AESGPU_OK
+    L.aesgpu_pipeline_destroy(None)
 
 
 def test_strerror_names_every_code(A):

@@ -1,0 +1,191 @@
+"""GPU parity of the host-staged pipeline (host buffers in and out, chunked
+upload / kernel / read-back on several streams) against the CPU oracle, for
+every mode, with pinned and pageable host memory, ragged chunk ends and
+in-place runs; plus its argument errors."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import log, requires_gpu
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+CHUNK = 64 << 10       # small chunks so that a few hundred KiB span many of them
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1201_0398_amd import aesgpu
+    return aesgpu
+
+
+@pytest.fixture(scope="module")
+def ctx(A):
+    c = A.aesgpu_create()
+    yield c
+    A.aesgpu_destroy(c)
+
+
+def expected(op, A, key, data, nonce, ctr0, iv):
+    if op == A.AESGPU_OP_ECB_ENCRYPT:
+        return oracle.ecb(key, data)
+    if op == A.AESGPU_OP_ECB_DECRYPT:
+        return oracle.ecb(key, data, decrypt=True)
+    if op == A.AESGPU_OP_CTR:
+        return oracle.ctr(key, nonce, ctr0, data)
+    if op == A.AESGPU_OP_CTR_LE128:
+        return oracle.ctr_le128(key, iv, 0, data)
+    return oracle.cbc_decrypt(key, iv, data)
+
+
+OPS = ["ECB_ENCRYPT", "ECB_DECRYPT", "CTR", "CTR_LE128", "CBC_DECRYPT"]
+
+
+# Host memory kinds: pageable (staged through pinned buffers), pinned with
+# zero copy (the kernel reads and writes host memory), pinned with DMA copies.
+MEMS = ["pageable", "zero_copy", "dma"]
+
+
+@pytest.mark.parametrize("opname", OPS)
+@pytest.mark.parametrize("mem", MEMS)
+def test_pipeline_matches_oracle(A, ctx, opname, mem):
+    op = getattr(A, f"AESGPU_OP_{opname}")
+    pinned = mem != "pageable"
+    flags = A.AESGPU_PIPELINE_COPY if mem == "dma" else 0
+    whole = op in (A.AESGPU_OP_ECB_ENCRYPT, A.AESGPU_OP_ECB_DECRYPT, A.AESGPU_OP_CBC_DECRYPT)
+    rng = np.random.default_rng(7000 + op + 10 * MEMS.index(mem))
+    kb = (16, 24, 32)[op % 3]
+    key = rng.integers(0, 256, kb, dtype=np.uint8)
+    k = A.aesgpu_expand_key(key)
+    nonce = rng.integers(0, 256, 12, dtype=np.uint8)
+    iv = rng.integers(0, 256, 16, dtype=np.uint8)
+    ctr0 = int(rng.integers(0, 1 << 20))
+    for n_slots in (1, 3):
+        pl = A.aesgpu_pipeline_create(ctx, CHUNK, n_slots, flags)
+        try:
+            for n in [16, CHUNK - 16, CHUNK, CHUNK + 16, 5 * CHUNK + 16 * 37]:
+                if not whole:
+                    n += 7
+                log(f"case: pipeline {opname} {mem} slots={n_slots} n={n}")
+                data = rng.integers(0, 256, n, dtype=np.uint8)
+                host = []
+                if pinned:
+                    a_in, h_in = A.aesgpu_host_alloc(n)
+                    a_out, h_out = A.aesgpu_host_alloc(n + 64)
+                    host = [a_in, a_out]
+                    h_in[:] = data
+                    h_out[:] = 0x5A
+                else:
+                    h_in = data.copy()
+                    h_out = np.full(n + 64, 0x5A, dtype=np.uint8)
+                try:
+                    o = A.make_host_op(op, ctr0=ctr0, nonce=nonce, iv=iv)
+                    A.aesgpu_pipeline_run(pl, k, o, h_in, h_out, n)
+                    want = expected(op, A, key, data, nonce, ctr0, iv)
+                    assert np.array_equal(np.asarray(h_out[:n]), want)
+                    assert (np.asarray(h_out[n:]) == 0x5A).all(), "wrote past the end"
+                    assert np.array_equal(np.asarray(h_in[:n]), data), "input modified"
+                finally:
+                    for a in host:
+                        A.aesgpu_host_free(a)
+        finally:
+            A.aesgpu_pipeline_destroy(pl)
+
+
+@pytest.mark.parametrize("mem", MEMS)
+def test_pipeline_in_place(A, ctx, mem):
+    pinned = mem != "pageable"
+    rng = np.random.default_rng(7100 + MEMS.index(mem))
+    key = rng.integers(0, 256, 16, dtype=np.uint8)
+    k = A.aesgpu_expand_key(key)
+    nonce = rng.integers(0, 256, 12, dtype=np.uint8)
+    n = 3 * CHUNK + 16 * 5 + 3
+    data = rng.integers(0, 256, n, dtype=np.uint8)
+    pl = A.aesgpu_pipeline_create(ctx, CHUNK, 2, A.AESGPU_PIPELINE_COPY if mem == "dma" else 0)
+    addr = None
+    try:
+        if pinned:
+            addr, buf = A.aesgpu_host_alloc(n)
+            buf[:] = data
+        else:
+            buf = data.copy()
+        A.aesgpu_pipeline_run(pl, k, A.make_host_op(A.AESGPU_OP_CTR, ctr0=9, nonce=nonce),
+                              buf, buf, n)
+        assert np.array_equal(np.asarray(buf), oracle.ctr(key, nonce, 9, data))
+        m = 3 * CHUNK
+        A.aesgpu_pipeline_run(pl, k, A.make_host_op(A.AESGPU_OP_ECB_ENCRYPT), buf, buf, m)
+        A.aesgpu_pipeline_run(pl, k, A.make_host_op(A.AESGPU_OP_ECB_DECRYPT), buf, buf, m)
+        assert np.array_equal(np.asarray(buf), oracle.ctr(key, nonce, 9, data))
+    finally:
+        if addr is not None:
+            A.aesgpu_host_free(addr)
+        A.aesgpu_pipeline_destroy(pl)
+
+
+@pytest.mark.parametrize("mem", ["zero_copy", "dma"])
+def test_pipeline_large_default_chunks(A, ctx, mem):
+    """64 MiB + a tail, pinned both ways (one zero-copy kernel, or 8 MiB DMA
+    chunks on 3 slots), compared on sampled blocks and by a full round trip."""
+    rng = np.random.default_rng(7200)
+    key = rng.integers(0, 256, 32, dtype=np.uint8)
+    k = A.aesgpu_expand_key(key)
+    nonce = rng.integers(0, 256, 12, dtype=np.uint8)
+    n = (64 << 20) + 16 * 1000 + 9
+    a_in, h_in = A.aesgpu_host_alloc(n)
+    a_out, h_out = A.aesgpu_host_alloc(n)
+    pl = A.aesgpu_pipeline_create(ctx, 0, 0, A.AESGPU_PIPELINE_COPY if mem == "dma" else 0)
+    try:
+        h_in[:] = rng.integers(0, 256, n, dtype=np.uint8)
+        o = A.make_host_op(A.AESGPU_OP_CTR, ctr0=1, nonce=nonce)
+        A.aesgpu_pipeline_run(pl, k, o, h_in, h_out, n)
+        n_full = n // 16
+        idx = np.unique(np.concatenate([np.arange(4), np.arange(n_full - 4, n_full),
+                                        rng.integers(0, n_full, 4096),
+                                        np.arange(8 << 16, (8 << 16) + 4)]))
+        got = np.asarray(h_out[:16 * n_full]).reshape(-1, 16)[idx]
+        want = oracle.ctr_sampled(key, nonce, 1, np.asarray(h_in), idx)
+        assert np.array_equal(got, want)
+        tail_want = oracle.ctr(key, nonce, 1 + n_full, np.asarray(h_in[16 * n_full:]))
+        assert np.array_equal(np.asarray(h_out[16 * n_full:]), tail_want)
+        A.aesgpu_pipeline_run(pl, k, o, h_out, h_out, n)
+        assert np.array_equal(np.asarray(h_out), np.asarray(h_in))
+    finally:
+        A.aesgpu_pipeline_destroy(pl)
+        A.aesgpu_host_free(a_in)
+        A.aesgpu_host_free(a_out)
+
+
+def test_pipeline_errors(A, ctx):
+    import ctypes
+    L = A.lib()
+    k = A.aesgpu_expand_key(bytes(16))
+    out = ctypes.c_void_p()
+    assert L.aesgpu_pipeline_create(ctx, 100, 2, 0, ctypes.byref(out)) == A.AESGPU_EINVAL
+    assert L.aesgpu_pipeline_create(ctx, 1 << 16, 17, 0, ctypes.byref(out)) == A.AESGPU_EINVAL
+    assert L.aesgpu_pipeline_create(ctx, 1 << 16, 2, 2, ctypes.byref(out)) == A.AESGPU_EINVAL
+    pl = A.aesgpu_pipeline_create(ctx, 1 << 16, 2)
+    try:
+        buf = np.zeros(4096, dtype=np.uint8)
+        other = np.zeros(4096, dtype=np.uint8)
+        run = lambda op, a, b, n: A.aesgpu_pipeline_run(pl, k, op, a, b, n, check=False)  # noqa: E731
+        assert run(A.make_host_op(7), buf, other, 4096) == A.AESGPU_EINVAL
+        assert run(A.make_host_op(A.AESGPU_OP_ECB_ENCRYPT), buf, other, 100) == A.AESGPU_EINVAL
+        assert run(A.make_host_op(A.AESGPU_OP_CBC_DECRYPT), buf, buf, 4096) == A.AESGPU_EINVAL
+        assert run(A.make_host_op(A.AESGPU_OP_CTR), buf, buf.ctypes.data + 16, 1024) == \
+            A.AESGPU_EINVAL
+        assert run(A.make_host_op(A.AESGPU_OP_CTR, ctr0=(1 << 32) - 2), buf, other, 48) == \
+            A.AESGPU_ECTR_OVERFLOW
+        assert run(A.make_host_op(A.AESGPU_OP_CTR), buf, other, 0) == A.AESGPU_OK
+        assert A.aesgpu_host_free(buf.ctypes.data, check=False) == A.AESGPU_EINVAL
+        # A pinned range that is not 16-byte aligned takes the staged path.
+        addr, pb = A.aesgpu_host_alloc(4096 + 64)
+        try:
+            pb[:] = np.arange(4096 + 64, dtype=np.uint8)
+            want = oracle.ecb(bytes(16), np.asarray(pb[8:8 + 4096]).copy())
+            assert run(A.make_host_op(A.AESGPU_OP_ECB_ENCRYPT), addr + 8, other, 4096) == \
+                A.AESGPU_OK
+            assert np.array_equal(other, want)
+        finally:
+            A.aesgpu_host_free(addr)
+    finally:
+        A.aesgpu_pipeline_destroy(pl)
