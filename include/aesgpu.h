@@ -144,7 +144,7 @@ int aesgpu_cbc_decrypt(aesgpu_ctx *ctx, const aesgpu_key *key, const uint8_t *iv
 /* Batched messages: one persistent launch per table set                     */
 /* ------------------------------------------------------------------------ */
 
-enum { AESGPU_MODE_ECB = 0, AESGPU_MODE_CTR = 1 };
+enum { AESGPU_MODE_ECB = 0, AESGPU_MODE_CTR = 1, AESGPU_MODE_CBC = 2 };
 enum { AESGPU_DIR_ENCRYPT = 0, AESGPU_DIR_DECRYPT = 1 };
 
 /*
@@ -152,7 +152,14 @@ enum { AESGPU_DIR_ENCRYPT = 0, AESGPU_DIR_DECRYPT = 1 };
  * d_in + in_off and its output d_out + out_off (both 16-byte aligned), its key
  * the raw key bytes at d_keys + 32 * key_slot.  ECB messages are whole blocks
  * and use `dir`; CTR messages (nonce || BE32(ctr0 + i), as
- * aesgpu_ctr_xcrypt()) may end in a partial block and ignore `dir`.
+ * aesgpu_ctr_xcrypt()) may end in a partial block and ignore `dir`.  CBC
+ * messages (section 3, Eq. (2)) are whole blocks and use `dir`; their 16-byte
+ * IV is the 16 bytes starting at `nonce` (nonce[0..11], then ctr0's bytes in
+ * memory order).  CBC decryption is block-parallel; CBC encryption is
+ * sequential within a message (the paper leaves it out for one stream), so a
+ * batch runs up to 64 such messages of one key size per wave, one per lane,
+ * in a launch of its own after the persistent one, and only batches of many
+ * short CBC-encrypt messages use the GPU well.
  */
 typedef struct {
     uint64_t in_off;
@@ -185,7 +192,8 @@ typedef struct {
     uint64_t out_bytes_needed; /* max(out_off + n_bytes) */
     uint32_t blocks_per_lane;
     uint32_t tile_blocks;
-    uint32_t launches;         /* persistent launches per run (0 or 1) */
+    uint32_t launches;         /* launches per run: 1 persistent launch (if any ECB, CTR or
+                                  CBC-decrypt blocks) + 1 if any CBC-encrypt messages */
 } aesgpu_batch_stats;
 
 typedef struct aesgpu_batch aesgpu_batch;
@@ -205,11 +213,14 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
 /*
  * Runs a planned batch on `stream`: every message is encrypted or decrypted
  * with its own key, expanded on the device inside the launch (FIPS-197
- * KeyExpansion, plus the equivalent-inverse-cipher keys for ECB decryption).
+ * KeyExpansion, plus the equivalent-inverse-cipher keys for decryption).
  * d_keys holds n_key_slots raw keys at a 32-byte stride (key bytes first);
  * d_in and d_out are in_bytes / out_bytes long and must hold every message
- * (EINVAL otherwise).  d_in == d_out runs in place; other overlap is EINVAL.
- * Messages whose outputs overlap each other give undefined output.  By
+ * (EINVAL otherwise).  d_in == d_out runs in place, except that a CBC-decrypt
+ * message whose input and output ranges meet is then EINVAL (each block
+ * reads its predecessor's ciphertext); other overlap of d_in and d_out is
+ * EINVAL.  Messages whose outputs overlap each other, or overlap a
+ * CBC-decrypt message's input, give undefined output.  By
  * default the launches are captured once into a hipGraph and replayed; the
  * graph is re-captured when d_keys, d_in or d_out change.  Calls on one plan
  * must not overlap in time (they share the plan's tile counters).

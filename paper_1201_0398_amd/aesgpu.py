@@ -44,6 +44,7 @@ class aesgpu_key(ctypes.Structure):
 
 AESGPU_MODE_ECB = 0
 AESGPU_MODE_CTR = 1
+AESGPU_MODE_CBC = 2
 AESGPU_DIR_ENCRYPT = 0
 AESGPU_DIR_DECRYPT = 1
 AESGPU_BATCH_NO_GRAPH = 1
@@ -294,9 +295,12 @@ def aesgpu_cbc_decrypt(ctx, key: aesgpu_key, iv, d_in, d_out, n_blocks: int | No
 
 # ---- batched messages ------------------------------------------------------------
 
-def make_msgs(in_off, out_off, n_bytes, key_slot, key_bits, mode, dir, nonce=None, ctr0=None):
+def make_msgs(in_off, out_off, n_bytes, key_slot, key_bits, mode, dir, nonce=None, ctr0=None,
+              iv=None):
     """Array of ``aesgpu_msg`` from per-message sequences (numpy or lists);
-    ``nonce`` is an (m, 12) uint8 array."""
+    ``nonce`` is an (m, 12) uint8 array.  ``iv`` (an (m, 16) uint8 array, for
+    CBC messages) fills the 16 bytes from ``nonce`` on, i.e. nonce and ctr0;
+    it is applied to the rows whose mode is CBC."""
     import numpy as np
     m = len(n_bytes)
     arr = (aesgpu_msg * m)()
@@ -314,6 +318,10 @@ def make_msgs(in_off, out_off, n_bytes, key_slot, key_bits, mode, dir, nonce=Non
     if nonce is not None:
         view["nonce"] = nonce
     view["ctr0"] = 1 if ctr0 is None else ctr0
+    if iv is not None:
+        cbc = np.asarray(mode) == AESGPU_MODE_CBC
+        ivs = np.asarray(iv, dtype=np.uint8).reshape(m, 16)
+        raw[cbc, 32:48] = ivs[cbc]
     return arr
 
 

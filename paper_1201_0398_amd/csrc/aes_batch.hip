@@ -5,8 +5,11 @@
 // * Host plan: every message is cut into message-pure tiles of at most
 //   `tile_blocks` blocks.  Tiles that need the forward tables (ECB
 //   encryption, CTR either way) and tiles that need the inverse tables (ECB
-//   decryption) form two queues, each sorted longest first, so that the short
-//   tiles fill the end of the launch.
+//   and CBC decryption) form two queues, each sorted longest first, so that
+//   the short tiles fill the end of the launch.  CBC encryption is sequential
+//   within a message, so CBC-encrypt messages form groups of up to 64 of one
+//   key size, one message per lane, run by a launch of their own (its round
+//   keys live in registers, which the block-parallel kernel cannot spare).
 // * Device: each workgroup (1024 threads, one per CU) stages its table set in
 //   LDS once.  Each wave then pulls tile numbers from an atomic counter until
 //   the queue is empty (every wave reaches that exit; no wave waits on
@@ -44,6 +47,8 @@ struct BatchParams {
     const uint8_t *in;
     uint8_t *out;
     const uint32_t *tables;
+    const uint32_t *cbc_list;  // message indices of the CBC-encryption groups
+    uint4 *cbc_dummy;          // 16 bytes nobody reads (stores with nothing to store)
 };
 
 // Wave-uniform reads of copy 0 of a table (every lane reads the same word, so
@@ -146,10 +151,6 @@ __device__ __forceinline__ uint32_t schedule_of(const uint32_t *lds, const Bases
     return kreg;
 }
 
-// One tile: nr rounds on BPL blocks per lane per step.  The round loop is not
-// unrolled and takes nr at run time: one short loop body serves all key
-// sizes, so the code a workgroup runs fits the instruction cache even when
-// each CU executes it only once (small batches).
 // A descriptor read through the scalar cache, word by word.
 template <class T>
 __device__ __forceinline__ T load_uniform(const T *src) {
@@ -175,6 +176,10 @@ __device__ __forceinline__ void counter_round1(const uint32_t *lds, const Bases 
     s[3] = cc.p[3] ^ tlook<0>(lds, w3, b.t[0]);
 }
 
+// One tile: nr rounds on BPL blocks per lane per step.  The round loop is not
+// unrolled and takes nr at run time: one short loop body serves all key
+// sizes, so the code a workgroup runs fits the instruction cache even when
+// each CU executes it only once (small batches).
 template <bool kInv, int BPL>
 __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, const BatchParams &p,
                                          const DevMsg &m, const Tile &tile) {
@@ -228,9 +233,24 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     const uint32_t bytes = lim > first ? 16u * uint32_t(lim - first) : 0u;
     const rsrc_t rin = buffer_rsrc(in + first, bytes);
     const rsrc_t rout = buffer_rsrc(out + first, bytes);
-    uint4 next[BPL];
+    // CBC decryption (Eq. (2)): every block is XORed with the ciphertext
+    // block before it (the IV for block 0), read through a resource that
+    // starts one block before the tile.  ECB-decrypt tiles issue the same
+    // loads on an empty range, so every tile has the same memory operations.
+    const bool cbc = kInv && m.mode == AESGPU_MODE_CBC;
+    const uint64_t pbase = first > 0 ? first - 1 : 0;
+    const uint32_t pshift = first > 0 ? 0u : 1u;  // block 0 has no predecessor
+    const rsrc_t rprev = buffer_rsrc(in + pbase, cbc && lim > first ? 16u * uint32_t(lim - pbase)
+                                                                    : 0u);
+    const uint32_t cbc_mask = cbc ? ~0u : 0u;
+    uint4 next[BPL], next_prev[BPL];
 #pragma unroll
     for (int j = 0; j < BPL; ++j) next[j] = buffer_load16(rin, (uint32_t(j) * 64u + lane) * 16u);
+    if constexpr (kInv) {
+#pragma unroll
+        for (int j = 0; j < BPL; ++j)
+            next_prev[j] = buffer_load16(rprev, (uint32_t(j) * 64u + lane - pshift) * 16u);
+    }
     {
         // In the loop a step's loads are followed by the previous step's
         // stores.  These stores have an empty range and write nothing; they
@@ -247,13 +267,21 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
         asm volatile("" : "+v"(kreg));
         const uint32_t step_off = uint32_t(base - first);
         uint32_t s[BPL][4];
-        uint4 d[BPL];
+        uint4 d[BPL], prev[BPL];
         uint32_t rk[4];
         round_key(kreg, 0, rk);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             d[j] = next[j];
             next[j] = buffer_load16(rin, (step_off + kStep + uint32_t(j) * 64u + lane) * 16u);
+        }
+        if constexpr (kInv) {
+#pragma unroll
+            for (int j = 0; j < BPL; ++j) {
+                prev[j] = next_prev[j];
+                next_prev[j] = buffer_load16(
+                    rprev, (step_off + kStep + uint32_t(j) * 64u + lane - pshift) * 16u);
+            }
         }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
@@ -295,6 +323,13 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                 o.z ^= d[j].z;
                 o.w ^= d[j].w;
             }
+            if constexpr (kInv) {
+                const bool b0 = base + uint64_t(j) * 64u + lane == 0;
+                o.x ^= (b0 ? m.nonce[0] : prev[j].x) & cbc_mask;
+                o.y ^= (b0 ? m.nonce[1] : prev[j].y) & cbc_mask;
+                o.z ^= (b0 ? m.nonce[2] : prev[j].z) & cbc_mask;
+                o.w ^= (b0 ? m.ctr0 : prev[j].w) & cbc_mask;
+            }
             buffer_store16(rout, (step_off + uint32_t(j) * 64u + lane) * 16u, o);
         }
     }
@@ -319,6 +354,119 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                 dst[lane] = src[lane] ^ uint8_t(w >> (8 * (lane & 3u)));
             }
         }
+    }
+}
+
+// S-box applied to each byte of w, per lane, from the lane's own copy of T0
+// (byte 1 of T0[x] is S(x)).
+__device__ __forceinline__ uint32_t sub_word_lane(const uint32_t *lds, const Bases &b,
+                                                  uint32_t w) {
+    return ((tlook<0>(lds, w, b.t[0]) >> 8) & 0xFFu) | (tlook<1>(lds, w, b.t[0]) & 0xFF00u) |
+           ((tlook<2>(lds, w, b.t[0]) << 8) & 0xFF0000u) |
+           ((tlook<3>(lds, w, b.t[0]) << 16) & 0xFF000000u);
+}
+
+// FIPS-197 KeyExpansion of each lane's own key into registers.
+template <int NR>
+__device__ __forceinline__ void expand_key_lane(const uint32_t *lds, const Bases &b,
+                                                const uint32_t (&key)[8],
+                                                uint32_t (&w)[4 * (NR + 1)]) {
+    constexpr int nk = NR - 6;
+#pragma unroll
+    for (int i = 0; i < nk; ++i) w[i] = key[i];
+    uint32_t rcon = 1;
+#pragma unroll
+    for (int i = nk; i < 4 * (NR + 1); ++i) {
+        uint32_t t = w[i - 1];
+        if (i % nk == 0) {
+            t = sub_word_lane(lds, b, (t >> 8) | (t << 24)) ^ rcon;
+            rcon = ((rcon << 1) ^ ((rcon >> 7) * 0x1Bu)) & 0xFFu;
+        } else if (nk == 8 && i % nk == 4) {
+            t = sub_word_lane(lds, b, t);
+        }
+        w[i] = w[i - nk] ^ t;
+    }
+}
+
+// CBC encryption (C_i = E_K(P_i ^ C_{i-1}), C_{-1} = IV, the inverse of Eq.
+// (2)) of a group of up to 64 messages of one key size, one message per lane,
+// each with its own key schedule in registers.  Blocks of a message are
+// sequential; lanes whose message has ended compute on and store nothing
+// (the group is sorted longest first).  Iteration i stores the previous block
+// and loads the next one before the rounds, so the only memory wait (for
+// block i, at the loop top) is on a load issued a whole block earlier.
+template <int NR>
+__device__ void cbc_encrypt_group(const uint32_t *lds, const Bases &b, const BatchParams &p,
+                                  const Tile &tile, uint64_t n_max) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const bool active = lane < tile.n_blocks;
+    DevMsg m{};
+    if (active) m = p.msgs[p.cbc_list[tile.msg + lane]];
+    uint32_t rk[4 * (NR + 1)];
+    if (p.sched) {
+        const uint32_t *w = p.sched + uint64_t(m.key_slot) * kSchedWords;
+#pragma unroll
+        for (int i = 0; i < 4 * (NR + 1); ++i) rk[i] = w[i];
+    } else {
+        const uint32_t *kp = reinterpret_cast<const uint32_t *>(p.keys + 32ull * m.key_slot);
+        uint32_t key[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) key[i] = i < NR - 6 ? kp[i] : 0u;
+        expand_key_lane<NR>(lds, b, key, rk);
+    }
+    const uint64_t n = active ? m.n_full : 0;
+    const uint64_t last = n ? n - 1 : 0;
+    // Every load and store is issued in every iteration (no branch), so the
+    // compiler can count them: a lane without a message reads and writes the
+    // dummy block; a lane whose message has ended rewrites its last block with
+    // the same value.
+    const uint4 *in = n ? reinterpret_cast<const uint4 *>(p.in + m.in_off) : p.cbc_dummy;
+    uint4 *out = n ? reinterpret_cast<uint4 *>(p.out + m.out_off) : p.cbc_dummy;
+    uint32_t c[4] = {m.nonce[0], m.nonce[1], m.nonce[2], m.ctr0};
+    uint4 pt = in[0];
+    for (uint64_t i = 0; i < n_max; ++i) {
+        uint32_t s[4] = {pt.x ^ c[0] ^ rk[0], pt.y ^ c[1] ^ rk[1], pt.z ^ c[2] ^ rk[2],
+                         pt.w ^ c[3] ^ rk[3]};
+        uint4 *dst = i == 0 ? p.cbc_dummy : out + (i - 1 < last ? i - 1 : last);
+        *dst = make_uint4(c[0], c[1], c[2], c[3]);
+        pt = in[i + 1 <= last ? i + 1 : last];
+        // Compiler barrier: keeps the load of the next block issued here,
+        // before the rounds, instead of sunk to the next iteration.
+        asm volatile("" ::: "memory");
+#pragma unroll
+        for (int r = 1; r < NR; ++r) mid_round<false>(lds, b, s, &rk[4 * r]);
+        last_round_fwd(lds, b, s, &rk[4 * NR]);
+        // A select, not a branch: c stays live across the rounds, so the
+        // registers the store above reads are not reused before it is done.
+#pragma unroll
+        for (int k = 0; k < 4; ++k) c[k] = i < n ? s[k] : c[k];
+    }
+    if (n) out[last] = make_uint4(c[0], c[1], c[2], c[3]);
+}
+
+// The CBC-encryption launch: forward tables in LDS, then wave w of the grid
+// takes groups w, w + (waves in the grid), ... (longest first).  Every wave
+// reaches the end of the list.  WG threads per workgroup, one workgroup per
+// CU: few waves per CU when there are few groups (each lane's chain of
+// blocks is latency-bound), 16 when there are many.
+template <int WG>
+__global__ __launch_bounds__(WG) void cbc_encrypt_kernel(BatchParams p, const Tile *groups,
+                                                         uint32_t n_groups) {
+    __shared__ uint32_t lds[kFwdWords];
+    stage_tables<false, WG>(lds, p.tables);
+    const Bases b = lane_bases();
+    const uint32_t waves = gridDim.x * (blockDim.x / 64u);
+    for (uint32_t g = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); g < n_groups;
+         g += waves) {
+        const Tile t = load_uniform(groups + __builtin_amdgcn_readfirstlane(g));
+        // The first message is the group's longest; all share one key size.
+        const DevMsg m0 = load_uniform(p.msgs + as_const(p.cbc_list)[t.msg]);
+        if (m0.nr == 10)
+            cbc_encrypt_group<10>(lds, b, p, t, m0.n_full);
+        else if (m0.nr == 12)
+            cbc_encrypt_group<12>(lds, b, p, t, m0.n_full);
+        else
+            cbc_encrypt_group<14>(lds, b, p, t, m0.n_full);
     }
 }
 
@@ -403,8 +551,8 @@ __global__ void reset_counters(uint32_t *c, uint32_t n) {
 template <int BPL>
 int enqueue_t(const BatchLaunch &L, hipStream_t s) {
     const uint32_t total = L.n_tiles[0] + L.n_tiles[1];
-    if (!total) return AESGPU_OK;
-    if (L.reset_counters)
+    if (!total && !L.n_cbc_groups) return AESGPU_OK;
+    if (L.reset_counters && total)
         hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, L.counters, 2u);
     // About one tile per wave for small batches, one workgroup per CU at most.
     constexpr uint32_t kWaves = kWG / 64;
@@ -423,8 +571,21 @@ int enqueue_t(const BatchLaunch &L, hipStream_t s) {
     }
     BatchParams p{L.msgs,     {L.tiles[0], L.tiles[1]}, {L.n_tiles[0], L.n_tiles[1]},
                   L.counters, fwd,  {fwd * kWaves, (grid - fwd) * kWaves},
-                  L.keys,     L.sched, L.in, L.out, L.tables};
-    hipLaunchKernelGGL((batch_kernel<BPL>), dim3(grid), dim3(kWG), 0, s, p);
+                  L.keys,     L.sched, L.in, L.out, L.tables, L.cbc_list, L.cbc_dummy};
+    if (L.n_tiles[0] + L.n_tiles[1])
+        hipLaunchKernelGGL((batch_kernel<BPL>), dim3(grid), dim3(kWG), 0, s, p);
+    if (L.n_cbc_groups) {
+        const uint32_t n_cu = uint32_t(L.n_cu);
+        if (L.n_cbc_groups <= 4 * n_cu) {
+            const uint32_t g = (L.n_cbc_groups + 3) / 4;
+            hipLaunchKernelGGL(cbc_encrypt_kernel<256>, dim3(g), dim3(256), 0, s, p,
+                               L.cbc_groups, L.n_cbc_groups);
+        } else {
+            const uint32_t g = std::min<uint32_t>((L.n_cbc_groups + 15) / 16, n_cu);
+            hipLaunchKernelGGL(cbc_encrypt_kernel<kWG>, dim3(g), dim3(kWG), 0, s, p,
+                               L.cbc_groups, L.n_cbc_groups);
+        }
+    }
     return hipGetLastError() == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
 }
 
@@ -435,18 +596,23 @@ int enqueue_batch(const BatchLaunch &L, hipStream_t s) {
 }
 
 int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vector<DevMsg> &dm,
-                std::vector<Tile> (&tiles)[2], BatchTotals &tot) {
+                std::vector<Tile> (&tiles)[2], std::vector<uint32_t> &cbc_list,
+                std::vector<Tile> &cbc_groups, BatchTotals &tot) {
     dm.resize(m);
     tiles[0].clear();
     tiles[1].clear();
+    cbc_list.clear();
+    cbc_groups.clear();
     tot = BatchTotals{};
+    std::vector<uint32_t> cbc_enc[3];   // CBC-encrypt messages per key size
     for (size_t i = 0; i < m; ++i) {
         const aesgpu_msg &x = msgs[i];
         if (x.key_bits != 128 && x.key_bits != 192 && x.key_bits != 256) return AESGPU_EKEYLEN;
-        if (x.mode != AESGPU_MODE_ECB && x.mode != AESGPU_MODE_CTR) return AESGPU_EINVAL;
+        if (x.mode != AESGPU_MODE_ECB && x.mode != AESGPU_MODE_CTR && x.mode != AESGPU_MODE_CBC)
+            return AESGPU_EINVAL;
         if (x.dir != AESGPU_DIR_ENCRYPT && x.dir != AESGPU_DIR_DECRYPT) return AESGPU_EINVAL;
         if ((x.in_off & 15u) || (x.out_off & 15u)) return AESGPU_EALIGN;
-        if (x.mode == AESGPU_MODE_ECB && (x.n_bytes & 15u)) return AESGPU_EINVAL;
+        if (x.mode != AESGPU_MODE_CTR && (x.n_bytes & 15u)) return AESGPU_EINVAL;
         if (x.n_bytes > (UINT64_MAX >> 1) || x.in_off > UINT64_MAX - x.n_bytes ||
             x.out_off > UINT64_MAX - x.n_bytes)
             return AESGPU_EINVAL;
@@ -463,14 +629,22 @@ int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vec
         d.nr = x.key_bits / 32 + 6;
         d.mode = x.mode;
         for (int c = 0; c < 3; ++c) d.nonce[c] = le32(x.nonce + 4 * c);
-        d.ctr0 = x.ctr0;
+        d.ctr0 = x.ctr0;   // CBC: IV bytes 12..15 as a little-endian word
         tot.total += x.n_bytes;
         if (x.n_bytes) {
             tot.in_end = std::max(tot.in_end, x.in_off + x.n_bytes);
             tot.out_end = std::max(tot.out_end, x.out_off + x.n_bytes);
             tot.max_slot = std::max(tot.max_slot, x.key_slot);
         }
-        const int set = (x.mode == AESGPU_MODE_ECB && x.dir == AESGPU_DIR_DECRYPT) ? 1 : 0;
+        if (x.mode == AESGPU_MODE_CBC && x.dir == AESGPU_DIR_ENCRYPT) {
+            if (n_blocks) cbc_enc[(x.key_bits - 128) / 64].push_back(uint32_t(i));
+            continue;
+        }
+        const bool inverse = x.mode != AESGPU_MODE_CTR && x.dir == AESGPU_DIR_DECRYPT;
+        if (x.mode == AESGPU_MODE_CBC && inverse && x.n_bytes &&
+            x.in_off < x.out_off + x.n_bytes && x.out_off < x.in_off + x.n_bytes)
+            tot.cbc_dec_self_overlap = true;
+        const int set = inverse ? 1 : 0;
         tot.blocks[set] += n_blocks;
         for (uint64_t f = 0; f < n_blocks; f += tile_blocks) {
             const uint64_t n = std::min<uint64_t>(tile_blocks, n_blocks - f);
@@ -480,6 +654,21 @@ int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vec
     for (auto &t : tiles)
         std::stable_sort(t.begin(), t.end(),
                          [](const Tile &a, const Tile &b) { return a.n_blocks > b.n_blocks; });
+    // CBC-encrypt groups: per key size, longest first, 64 messages (lanes)
+    // per group; all groups longest first, since each runs its blocks one
+    // after another.
+    for (auto &v : cbc_enc) {
+        std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) {
+            return dm[a].n_full > dm[b].n_full;
+        });
+        for (size_t g = 0; g < v.size(); g += 64) {
+            const size_t n = std::min<size_t>(64, v.size() - g);
+            cbc_groups.push_back(Tile{uint32_t(cbc_list.size()), uint32_t(n), dm[v[g]].n_full});
+            cbc_list.insert(cbc_list.end(), v.begin() + long(g), v.begin() + long(g + n));
+        }
+    }
+    std::stable_sort(cbc_groups.begin(), cbc_groups.end(),
+                     [](const Tile &a, const Tile &b) { return a.first_block > b.first_block; });
     return AESGPU_OK;
 }
 
@@ -504,6 +693,10 @@ struct aesgpu_batch {
     DevMsg *d_msgs = nullptr;
     Tile *d_tiles[2] = {nullptr, nullptr};
     uint32_t *d_counters = nullptr;
+    Tile *d_cbc_groups = nullptr;
+    uint32_t *d_cbc_list = nullptr;
+    uint4 *d_cbc_dummy = nullptr;
+    size_t n_cbc_groups = 0;
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -533,6 +726,10 @@ int enqueue(aesgpu_batch *b, const uint8_t *keys, const void *in, void *out, hip
     L.in = static_cast<const uint8_t *>(in);
     L.out = static_cast<uint8_t *>(out);
     L.tables = b->ctx->d_tables;
+    L.cbc_list = b->d_cbc_list;
+    L.cbc_groups = b->d_cbc_groups;
+    L.cbc_dummy = b->d_cbc_dummy;
+    L.n_cbc_groups = uint32_t(b->n_cbc_groups);
     L.n_cu = b->ctx->n_cu;
     L.bpl = b->bpl;
     L.blocks[0] = b->tot.blocks[0];
@@ -563,10 +760,14 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
 
     std::vector<DevMsg> dm;
     std::vector<Tile> tiles[2];
+    std::vector<uint32_t> cbc_list;
+    std::vector<Tile> cbc_groups;
     BatchTotals tot;
-    const int st = build_tiles(msgs, m, tile_blocks, dm, tiles, tot);
+    const int st = build_tiles(msgs, m, tile_blocks, dm, tiles, cbc_list, cbc_groups, tot);
     if (st != AESGPU_OK) return st;
-    if (tiles[0].size() > 0xFFFFFFFFull || tiles[1].size() > 0xFFFFFFFFull) return AESGPU_EINVAL;
+    if (tiles[0].size() > 0xFFFFFFFFull || tiles[1].size() > 0xFFFFFFFFull ||
+        cbc_groups.size() > 0xFFFFFFFFull)
+        return AESGPU_EINVAL;
 
     aesgpu_batch *b = new (std::nothrow) aesgpu_batch;
     if (!b) return AESGPU_ENOMEM;
@@ -577,6 +778,7 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     b->n_msgs = m;
     b->n_tiles[0] = tiles[0].size();
     b->n_tiles[1] = tiles[1].size();
+    b->n_cbc_groups = cbc_groups.size();
     b->tot = tot;
 
     DeviceGuard g(ctx->device);
@@ -586,7 +788,10 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     }
     const size_t msg_bytes = m * sizeof(DevMsg);
     const size_t t0 = tiles[0].size() * sizeof(Tile), t1 = tiles[1].size() * sizeof(Tile);
-    const size_t bytes = msg_bytes + t0 + t1 + kCounterBytes;
+    const size_t cg = cbc_groups.size() * sizeof(Tile);
+    const size_t cl = cbc_list.size() * sizeof(uint32_t);
+    const size_t dummy = cg ? 16 : 0;
+    const size_t bytes = msg_bytes + t0 + t1 + kCounterBytes + cg + dummy + cl;
     if (hipMalloc(&b->d_mem, bytes) != hipSuccess) {
         delete b;
         return AESGPU_ENOMEM;
@@ -596,7 +801,17 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     b->d_tiles[0] = reinterpret_cast<Tile *>(base + msg_bytes);
     b->d_tiles[1] = reinterpret_cast<Tile *>(base + msg_bytes + t0);
     b->d_counters = reinterpret_cast<uint32_t *>(base + msg_bytes + t0 + t1);
+    b->d_cbc_groups = reinterpret_cast<Tile *>(base + msg_bytes + t0 + t1 + kCounterBytes);
+    b->d_cbc_dummy = reinterpret_cast<uint4 *>(base + msg_bytes + t0 + t1 + kCounterBytes + cg);
+    b->d_cbc_list =
+        reinterpret_cast<uint32_t *>(base + msg_bytes + t0 + t1 + kCounterBytes + cg + dummy);
     bool ok = true;
+    if (cg)
+        ok &= hipMemcpy(b->d_cbc_groups, cbc_groups.data(), cg, hipMemcpyHostToDevice) ==
+              hipSuccess;
+    if (!cbc_list.empty())
+        ok &= hipMemcpy(b->d_cbc_list, cbc_list.data(), cbc_list.size() * sizeof(uint32_t),
+                        hipMemcpyHostToDevice) == hipSuccess;
     if (msg_bytes) ok &= hipMemcpy(b->d_msgs, dm.data(), msg_bytes, hipMemcpyHostToDevice) == hipSuccess;
     if (t0) ok &= hipMemcpy(b->d_tiles[0], tiles[0].data(), t0, hipMemcpyHostToDevice) == hipSuccess;
     if (t1) ok &= hipMemcpy(b->d_tiles[1], tiles[1].data(), t1, hipMemcpyHostToDevice) == hipSuccess;
@@ -612,7 +827,7 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
 int aesgpu_batch_run(aesgpu_batch *b, const uint8_t *d_keys, size_t n_key_slots, const void *d_in,
                      size_t in_bytes, void *d_out, size_t out_bytes, aesgpu_stream_t stream) {
     if (!b) return AESGPU_EINVAL;
-    if (b->n_tiles[0] + b->n_tiles[1] == 0) return AESGPU_OK;
+    if (b->n_tiles[0] + b->n_tiles[1] + b->n_cbc_groups == 0) return AESGPU_OK;
     if (!d_keys || !d_in || !d_out) return AESGPU_EINVAL;
     if ((reinterpret_cast<uintptr_t>(d_keys) | reinterpret_cast<uintptr_t>(d_in) |
          reinterpret_cast<uintptr_t>(d_out)) & 15u)
@@ -621,6 +836,7 @@ int aesgpu_batch_run(aesgpu_batch *b, const uint8_t *d_keys, size_t n_key_slots,
     if (b->tot.in_end > in_bytes || b->tot.out_end > out_bytes) return AESGPU_EINVAL;
     const uintptr_t i0 = reinterpret_cast<uintptr_t>(d_in), o0 = reinterpret_cast<uintptr_t>(d_out);
     if (i0 != o0 && i0 < o0 + out_bytes && o0 < i0 + in_bytes) return AESGPU_EINVAL;
+    if (i0 == o0 && b->tot.cbc_dec_self_overlap) return AESGPU_EINVAL;
     DeviceGuard g(b->ctx->device);
     if (!g.ok()) return AESGPU_EHIP;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -658,7 +874,7 @@ int aesgpu_batch_info(const aesgpu_batch *b, aesgpu_batch_stats *out) {
     out->out_bytes_needed = b->tot.out_end;
     out->blocks_per_lane = b->bpl;
     out->tile_blocks = b->tile_blocks;
-    out->launches = (b->n_tiles[0] + b->n_tiles[1]) ? 1u : 0u;
+    out->launches = ((b->n_tiles[0] + b->n_tiles[1]) ? 1u : 0u) + (b->n_cbc_groups ? 1u : 0u);
     return AESGPU_OK;
 }
 

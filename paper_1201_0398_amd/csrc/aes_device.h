@@ -126,32 +126,38 @@ __device__ __forceinline__ void last_round_inv(const uint32_t *lds, const Bases 
 
 // Copies the table set into the LDS image.  Loads are issued in groups of
 // eight before their LDS writes, so the staging costs a few L2 round trips
-// instead of one per word, with few registers live.  Needs blockDim.x == kWG.
-template <bool kInv>
+// instead of one per word, with few registers live.  Needs blockDim.x == WG.
+template <bool kInv, int WG = kWG>
 __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ g) {
+    static_assert(kFwdWords % (WG * 8) == 0 && kInvSWords % WG == 0, "workgroup size");
     const uint32_t *src = g + (kInv ? kTd : kTe);
-    constexpr int kPer = kFwdWords / kWG;
+    constexpr int kPer = kFwdWords / WG;
     constexpr int kGroup = 8;
 #pragma unroll 1
     for (int k0 = 0; k0 < kPer; k0 += kGroup) {
         uint32_t v[kGroup];
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
-            const uint32_t i = threadIdx.x + uint32_t(k0 + k) * kWG;
+            const uint32_t i = threadIdx.x + uint32_t(k0 + k) * WG;
             const uint32_t t = ((i >> 14) << 1) | ((i >> 5) & 1u);
             const uint32_t x = (i >> 6) & 0xFFu;
             v[k] = src[t * 256u + x];
         }
 #pragma unroll
-        for (int k = 0; k < kGroup; ++k) lds[threadIdx.x + uint32_t(k0 + k) * kWG] = v[k];
+        for (int k = 0; k < kGroup; ++k) lds[threadIdx.x + uint32_t(k0 + k) * WG] = v[k];
     }
     if constexpr (kInv) {
-        constexpr int kPerS = kInvSWords / kWG;
-        uint32_t w[kPerS];
+        constexpr int kPerS = kInvSWords / WG;
+#pragma unroll 1
+        for (int k0 = 0; k0 < kPerS; k0 += 8) {
+            uint32_t w[8];
 #pragma unroll
-        for (int k = 0; k < kPerS; ++k) w[k] = g[kInvSS + ((threadIdx.x + uint32_t(k) * kWG) >> 5)];
+            for (int k = 0; k < 8; ++k)
+                w[k] = k0 + k < kPerS ? g[kInvSS + ((threadIdx.x + uint32_t(k0 + k) * WG) >> 5)] : 0u;
 #pragma unroll
-        for (int k = 0; k < kPerS; ++k) lds[kFwdWords + threadIdx.x + uint32_t(k) * kWG] = w[k];
+            for (int k = 0; k < 8; ++k)
+                if (k0 + k < kPerS) lds[kFwdWords + threadIdx.x + uint32_t(k0 + k) * WG] = w[k];
+        }
     }
     __syncthreads();
 }

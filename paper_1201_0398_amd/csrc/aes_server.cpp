@@ -233,8 +233,10 @@ int launch_slot(aesgpu_server *s, Slot &slot) {
     }
     std::vector<DevMsg> dm;
     std::vector<Tile> tiles[2];
+    std::vector<uint32_t> cbc_list;   // stay empty: served requests are ECB
+    std::vector<Tile> cbc_groups;
     BatchTotals tot;
-    int st = build_tiles(msgs.data(), m, tile_blocks, dm, tiles, tot);
+    int st = build_tiles(msgs.data(), m, tile_blocks, dm, tiles, cbc_list, cbc_groups, tot);
     if (st != AESGPU_OK) return st;
     const size_t mb = m * sizeof(DevMsg), t0 = tiles[0].size() * sizeof(Tile),
                  t1 = tiles[1].size() * sizeof(Tile);
@@ -264,6 +266,10 @@ int launch_slot(aesgpu_server *s, Slot &slot) {
     L.in = nullptr;
     L.out = s->d_arena;
     L.tables = s->ctx->d_tables;
+    L.cbc_list = nullptr;
+    L.cbc_groups = nullptr;
+    L.cbc_dummy = nullptr;
+    L.n_cbc_groups = 0;
     L.n_cu = s->ctx->n_cu;
     L.bpl = s->cfg.blocks_per_lane;
     L.blocks[0] = tot.blocks[0];

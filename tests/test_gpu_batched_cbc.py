@@ -1,0 +1,166 @@
+"""GPU parity of CBC inside the batched launch: block-parallel CBC decryption
+tiles and the CBC-encryption launch (one message per lane, groups of up to 64
+messages of one key size), mixed with ECB and CTR messages, against the CPU
+oracle run on each message alone; in-place rules and plan validation."""
+import numpy as np
+import pytest
+
+import oracle
+from gpu_common import from_dev, log, requires_gpu, to_dev
+
+pytestmark = [pytest.mark.gpu, requires_gpu]
+
+
+@pytest.fixture(scope="module")
+def A():
+    from paper_1201_0398_amd import aesgpu
+    return aesgpu
+
+
+@pytest.fixture(scope="module")
+def ctx(A):
+    c = A.aesgpu_create()
+    yield c
+    A.aesgpu_destroy(c)
+
+
+def _batch(rng, m, modes, max_blocks=512):
+    """m messages with the given modes (0 ECB, 1 CTR, 2 CBC), random
+    directions, key sizes, lengths and gaps; CBC and ECB whole blocks."""
+    blocks = rng.integers(1, max_blocks + 1, size=m)
+    lengths = 16 * blocks
+    tail = rng.integers(0, 16, size=m)
+    lengths = np.where(modes == 1, np.maximum(lengths - tail, 1), lengths)
+    bits = np.array([128, 192, 256])[rng.integers(0, 3, size=m)]
+    dirs = rng.integers(0, 2, size=m)
+    pad = 16 * rng.integers(0, 3, size=m)
+    span = 16 * ((lengths + 15) // 16) + pad
+    in_off = np.concatenate([[0], np.cumsum(span)[:-1]])
+    out_off = np.concatenate([[0], np.cumsum(span[::-1])[:-1]])[::-1].copy()
+    keys = np.zeros((m, 32), dtype=np.uint8)
+    for j in range(m):
+        keys[j, : bits[j] // 8] = rng.integers(0, 256, bits[j] // 8, dtype=np.uint8)
+    nonces = rng.integers(0, 256, (m, 12), dtype=np.uint8)
+    ctr0 = rng.integers(0, 1 << 31, size=m).astype(np.uint32)
+    ivs = rng.integers(0, 256, (m, 16), dtype=np.uint8)
+    total = int(span.sum())
+    data = rng.integers(0, 256, total, dtype=np.uint8)
+    return dict(lengths=lengths, modes=modes, bits=bits, dirs=dirs, in_off=in_off,
+                out_off=out_off, keys=keys, nonces=nonces, ctr0=ctr0, ivs=ivs, data=data,
+                total=total, m=m)
+
+
+def _expected(b, j, data=None):
+    data = b["data"] if data is None else data
+    L = int(b["lengths"][j])
+    key = b["keys"][j, : b["bits"][j] // 8]
+    src = data[b["in_off"][j]: b["in_off"][j] + L]
+    if b["modes"][j] == 1:
+        return oracle.ctr(key, b["nonces"][j], int(b["ctr0"][j]), src)
+    if b["modes"][j] == 2:
+        if b["dirs"][j]:
+            return oracle.cbc_decrypt(key, b["ivs"][j], src)
+        return oracle.cbc_encrypt(key, b["ivs"][j], src)
+    return oracle.ecb(key, src, decrypt=bool(b["dirs"][j]))
+
+
+def _msgs(A, b, dirs=None):
+    return A.make_msgs(b["in_off"], b["out_off"], b["lengths"], np.arange(b["m"]), b["bits"],
+                       b["modes"], b["dirs"] if dirs is None else dirs, b["nonces"], b["ctr0"],
+                       iv=b["ivs"])
+
+
+def _run_and_check(A, ctx, b, **kw):
+    import torch
+    plan = A.aesgpu_batch_plan(ctx, _msgs(A, b), **kw)
+    try:
+        st = A.aesgpu_batch_info(plan)
+        has_enc = bool(((b["modes"] == 2) & (b["dirs"] == 0)).any())
+        has_block = bool(((b["modes"] != 2) | (b["dirs"] == 1)).any())
+        assert st.launches == int(has_enc) + int(has_block)
+        d_keys = to_dev(b["keys"].reshape(-1))
+        d_in = to_dev(b["data"])
+        d_out = torch.full((b["total"],), 0x5A, dtype=torch.uint8, device="cuda")
+        for _ in range(2):    # a graph replay (or a second direct run) too
+            A.aesgpu_batch_run(plan, d_keys, b["m"], d_in, d_out)
+        out = from_dev(d_out)
+        covered = np.zeros(b["total"], dtype=bool)
+        for j in range(b["m"]):
+            o, L = int(b["out_off"][j]), int(b["lengths"][j])
+            assert np.array_equal(out[o:o + L], _expected(b, j)), \
+                f"message {j}: mode {b['modes'][j]} dir {b['dirs'][j]} bits {b['bits'][j]} len {L}"
+            covered[o:o + L] = True
+        assert (out[~covered] == 0x5A).all(), "wrote outside the messages"
+    finally:
+        A.aesgpu_batch_free(plan)
+
+
+@pytest.mark.parametrize("bpl,graph", [(1, True), (2, True), (2, False)])
+def test_mixed_batch_with_cbc(A, ctx, bpl, graph):
+    rng = np.random.default_rng(9000 + bpl + 10 * graph)
+    m = 600
+    modes = rng.integers(0, 3, size=m)
+    b = _batch(rng, m, modes)
+    log(f"case: mixed ECB/CTR/CBC batch of {m}, bpl={bpl} graph={graph}, {b['total']} bytes")
+    flags = 0 if graph else A.AESGPU_BATCH_NO_GRAPH
+    _run_and_check(A, ctx, b, blocks_per_lane=bpl, tile_blocks=128 * bpl, flags=flags)
+
+
+@pytest.mark.parametrize("m", [1, 63, 64, 65, 200, 1000])
+def test_cbc_only_batches(A, ctx, m):
+    """Only CBC messages: encrypt groups of up to 64 per key size (full,
+    partial and many groups), and decrypt tiles."""
+    rng = np.random.default_rng(9100 + m)
+    b = _batch(rng, m, np.full(m, 2), max_blocks=300)
+    log(f"case: CBC-only batch of {m}")
+    _run_and_check(A, ctx, b)
+    b["dirs"][:] = 0                    # encrypt only: one launch
+    _run_and_check(A, ctx, b)
+
+
+def test_cbc_round_trip_and_in_place(A, ctx):
+    import torch
+    rng = np.random.default_rng(9200)
+    m = 150
+    b = _batch(rng, m, np.full(m, 2), max_blocks=700)
+    b["out_off"] = b["in_off"].copy()                     # in place layout
+    d_keys = to_dev(b["keys"].reshape(-1))
+    buf = to_dev(b["data"])
+    enc = A.aesgpu_batch_plan(ctx, _msgs(A, b, dirs=np.zeros(m, dtype=np.int64)))
+    dec = A.aesgpu_batch_plan(ctx, _msgs(A, b, dirs=np.ones(m, dtype=np.int64)))
+    try:
+        A.aesgpu_batch_run(enc, d_keys, m, buf, buf)      # CBC encryption in place
+        ct = from_dev(buf)
+        bb = dict(b, dirs=np.zeros(m, dtype=np.int64))
+        for j in range(m):
+            o, L = int(b["in_off"][j]), int(b["lengths"][j])
+            assert np.array_equal(ct[o:o + L], _expected(bb, j)), f"message {j}"
+        # CBC decryption in place is refused; out of place it restores the data.
+        st = A.aesgpu_batch_run(dec, d_keys, m, buf, buf, check=False)
+        assert st == A.AESGPU_EINVAL
+        out = torch.zeros_like(buf)
+        A.aesgpu_batch_run(dec, d_keys, m, buf, out)
+        pt = from_dev(out)
+        for j in range(m):
+            o, L = int(b["in_off"][j]), int(b["lengths"][j])
+            assert np.array_equal(pt[o:o + L], b["data"][o:o + L]), f"message {j}"
+    finally:
+        A.aesgpu_batch_free(enc)
+        A.aesgpu_batch_free(dec)
+
+
+def test_cbc_plan_validation(A, ctx):
+    import ctypes
+    msgs = A.make_msgs([0], [0], [24], [0], [128], [A.AESGPU_MODE_CBC], [0])
+    out = ctypes.c_void_p()
+    L = A.lib()
+    assert L.aesgpu_batch_plan(ctx, msgs, 1, None, ctypes.byref(out)) == A.AESGPU_EINVAL
+    msgs = A.make_msgs([0], [0], [32], [0], [128], [3], [0])
+    assert L.aesgpu_batch_plan(ctx, msgs, 1, None, ctypes.byref(out)) == A.AESGPU_EINVAL
+    # A zero-length CBC message is valid and does nothing.
+    msgs = A.make_msgs([0, 0], [0, 16], [0, 16], [0, 0], [128, 128], [2, 2], [0, 0])
+    plan = A.aesgpu_batch_plan(ctx, msgs)
+    try:
+        assert A.aesgpu_batch_info(plan).launches == 1
+    finally:
+        A.aesgpu_batch_free(plan)
