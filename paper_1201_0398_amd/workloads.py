@@ -107,6 +107,40 @@ def batched(seed: int = 3, m: int = 65536, lo: int = 16, hi: int = 1 << 20) -> B
 
 
 @dataclass
+class CbcBatch:
+    lengths: np.ndarray     # bytes per message (16-byte multiples)
+    offsets: np.ndarray     # packed input offsets (outputs use the same)
+    key_bits: np.ndarray
+    keys: np.ndarray        # (m, 32) uint8, left-aligned
+    ivs: np.ndarray         # (m, 16) uint8
+    data: np.ndarray
+
+    @property
+    def total_bytes(self) -> int:
+        return int(self.lengths.sum())
+
+
+def cbc_batch(seed: int = 6, m: int = 65536, lo: int = 16, hi: int = 1 << 14) -> CbcBatch:
+    """Many short CBC messages (the case where CBC encryption, sequential
+    within a message, can use a GPU): log-uniform lengths, key size uniform
+    over 128/192/256, per message a key then an IV, then the packed data."""
+    rng = np.random.default_rng(seed)
+    lengths = log_uniform_lengths(rng, m, lo, hi)
+    key_bits = np.asarray(KEY_BITS)[rng.integers(0, 3, size=m)]
+    keys = np.zeros((m, 32), dtype=np.uint8)
+    ivs = np.zeros((m, 16), dtype=np.uint8)
+    for j in range(m):
+        nb = int(key_bits[j]) // 8
+        keys[j, :nb] = _bytes(rng, nb)
+        ivs[j] = _bytes(rng, 16)
+    offsets = np.zeros(m, dtype=np.int64)
+    if m > 1:
+        offsets[1:] = np.cumsum(lengths)[:-1]
+    data = _bytes(rng, int(lengths.sum()))
+    return CbcBatch(lengths, offsets, key_bits.astype(np.int64), keys, ivs, data)
+
+
+@dataclass
 class ServingTrace:
     pool_bits: np.ndarray   # (n_keys,) 128/192/256
     pool_keys: np.ndarray   # (n_keys, 32) uint8, left-aligned
