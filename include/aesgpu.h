@@ -157,9 +157,9 @@ enum { AESGPU_DIR_ENCRYPT = 0, AESGPU_DIR_DECRYPT = 1 };
  * IV is the 16 bytes starting at `nonce` (nonce[0..11], then ctr0's bytes in
  * memory order).  CBC decryption is block-parallel; CBC encryption is
  * sequential within a message (the paper leaves it out for one stream), so a
- * batch runs up to 64 such messages of one key size per wave, one per lane,
- * in a launch of its own after the persistent one, and only batches of many
- * short CBC-encrypt messages use the GPU well.
+ * batch runs up to 16 such messages of one key size per wave, four lanes per
+ * message, in a launch of its own after the persistent one, and only batches
+ * of many short CBC-encrypt messages use the GPU well.
  */
 typedef struct {
     uint64_t in_off;

@@ -1,0 +1,92 @@
+// Internal declarations of the batched launches (planner, persistent
+// launch, CBC-encryption launch), shared by the batch and server sources.
+#pragma once
+
+#include <vector>
+
+#include "aes_internal.h"
+
+namespace aesgpu {
+
+// Device descriptor of one message (64 bytes).
+struct alignas(16) DevMsg {
+    uint64_t in_off;
+    uint64_t out_off;
+    uint64_t n_full;    // whole blocks
+    uint32_t tail;      // bytes of a final partial block (CTR only)
+    uint32_t key_slot;
+    uint32_t nr;
+    uint32_t mode;      // AESGPU_MODE_ECB / CTR / CBC
+    uint32_t nonce[3];  // CTR nonce words; CBC: IV words 0..2
+    uint32_t ctr0;      // CTR first counter; CBC: IV word 3
+    uint32_t pad[2];
+};
+static_assert(sizeof(DevMsg) == 64, "descriptor layout");
+
+// A message-pure run of blocks (16 bytes), or a CBC-encryption group.
+struct alignas(16) Tile {
+    uint32_t msg;
+    uint32_t n_blocks;      // blocks in this tile (the partial CTR block counts)
+    uint64_t first_block;   // first block of the tile within its message
+};
+static_assert(sizeof(Tile) == 16, "tile layout");
+
+// A CBC-encryption group (same 16-byte layout): up to kCbcGroupMsgs
+// CBC-encrypt messages of one key size, four lanes each (encryption is
+// sequential within a message); msg is the group's first index into the CBC
+// list, n_blocks its message count, first_block its longest message's block
+// count.
+constexpr uint32_t kCbcGroupMsgs = 16;
+
+// Words per key slot of a resident schedule: 64 encryption words (60 used)
+// followed by 64 equivalent-inverse-cipher words.
+constexpr uint32_t kSchedWords = 128;
+
+// Device bytes after the tiles: 2 queue counters (zero before each run) and
+// one scratch flag per workgroup (at most 1024 workgroups).
+constexpr size_t kCounterBytes = 4 * (2 + 1024) + 56;
+
+struct BatchTotals {
+    uint64_t total = 0;    // sum of message bytes
+    uint64_t blocks[2] = {0, 0};  // blocks per table set
+    uint64_t in_end = 0;   // max(in_off + n_bytes)
+    uint64_t out_end = 0;  // max(out_off + n_bytes)
+    uint32_t max_slot = 0;
+    bool cbc_dec_self_overlap = false;  // a CBC-decrypt message whose input and output ranges meet
+};
+
+// Everything one batched run needs on the device.  Set 0 is the forward
+// table set (ECB encryption, CTR), set 1 the inverse set (ECB decryption).
+// Both sets run in one launch.
+struct BatchLaunch {
+    const DevMsg *msgs;
+    const Tile *tiles[2];
+    uint32_t n_tiles[2];
+    uint32_t *counters;      // kCounterBytes: two tile counters, then per-workgroup flags
+    const uint8_t *keys;     // raw keys (expanded on the device), or
+    const uint32_t *sched;   // resident schedules (kSchedWords per slot)
+    const uint8_t *in;
+    uint8_t *out;
+    const uint32_t *tables;
+    const uint32_t *cbc_list;  // message indices of the CBC-encryption groups
+    const Tile *cbc_groups;    // the groups, longest first (own launch)
+    uint4 *cbc_dummy;          // 16 scratch bytes for stores with nothing to store
+    uint32_t n_cbc_groups;
+    int n_cu;
+    uint32_t bpl;
+    uint64_t blocks[2];      // blocks per set, to split the workgroups
+    bool reset_counters;     // launch a counter reset first (else already zero)
+};
+
+// Validates messages and cuts them into tiles of at most tile_blocks blocks,
+// each queue sorted longest first; CBC-encrypt messages form groups (per key
+// size, longest first, listed in cbc_list) for their own launch.
+int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vector<DevMsg> &dm,
+                std::vector<Tile> (&tiles)[2], std::vector<uint32_t> &cbc_list,
+                std::vector<Tile> &cbc_groups, BatchTotals &tot);
+
+// Optional counter reset, then one persistent launch over both queues, then
+// (if the batch has CBC-encrypt messages) the CBC-encryption launch.
+int enqueue_batch(const BatchLaunch &L, hipStream_t stream);
+
+}  // namespace aesgpu

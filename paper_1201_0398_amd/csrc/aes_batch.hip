@@ -7,9 +7,10 @@
 //   encryption, CTR either way) and tiles that need the inverse tables (ECB
 //   and CBC decryption) form two queues, each sorted longest first, so that
 //   the short tiles fill the end of the launch.  CBC encryption is sequential
-//   within a message, so CBC-encrypt messages form groups of up to 64 of one
-//   key size, one message per lane, run by a launch of their own (its round
-//   keys live in registers, which the block-parallel kernel cannot spare).
+//   within a message, so CBC-encrypt messages form groups of up to 16 of one
+//   key size, four lanes per message (one state column each), run by a
+//   launch of their own (its round keys live in registers, which the
+//   block-parallel kernel cannot spare).
 // * Device: each workgroup (1024 threads, one per CU) stages its table set in
 //   LDS once.  Each wave then pulls tile numbers from an atomic counter until
 //   the queue is empty (every wave reaches that exit; no wave waits on
@@ -28,6 +29,7 @@
 #include <vector>
 
 #include "aes_device.h"
+#include "aes_batch.h"
 #include "aes_internal.h"
 
 namespace aesgpu {
@@ -366,82 +368,118 @@ __device__ __forceinline__ uint32_t sub_word_lane(const uint32_t *lds, const Bas
            ((tlook<3>(lds, w, b.t[0]) << 16) & 0xFF000000u);
 }
 
-// FIPS-197 KeyExpansion of each lane's own key into registers.
+// Lane q of each group of four lanes receives the value of lane (q + K) mod 4
+// of its group (a DPP quad permutation).
+template <int K>
+__device__ __forceinline__ uint32_t quad_rot(uint32_t v) {
+    constexpr int kSel = ((0 + K) & 3) | (((1 + K) & 3) << 2) | (((2 + K) & 3) << 4) |
+                         (((3 + K) & 3) << 6);
+    return __builtin_amdgcn_update_dpp(0u, v, kSel, 0xF, 0xF, true);
+}
+
+// One round of Eq. (1) on a block held by four lanes, lane q holding state
+// word q: output word q reads byte k of word q + k (mod 4), which the quad
+// permutations bring to lane q.  The last round takes the S-box bytes from
+// the T tables as last_round_fwd does.
+template <bool kLast>
+__device__ __forceinline__ uint32_t quad_round(const uint32_t *lds, const Bases &b, uint32_t s,
+                                               uint32_t k) {
+    const uint32_t s1 = quad_rot<1>(s), s2 = quad_rot<2>(s), s3 = quad_rot<3>(s);
+    if constexpr (kLast)
+        return merge4_xor(tlook<0>(lds, s, b.t[2]), tlook<1>(lds, s1, b.t[3]),
+                          tlook<2>(lds, s2, b.t[0]), tlook<3>(lds, s3, b.t[1]), k);
+    return xor3(xor3(tlook<0>(lds, s, b.t[0]), tlook<1>(lds, s1, b.t[1]),
+                     tlook<2>(lds, s2, b.t[2])),
+                tlook<3>(lds, s3, b.t[3]), k);
+}
+
+// FIPS-197 KeyExpansion of the quad's key; lane q keeps column q of every
+// round key (rk[r] = word 4r + q).  Only the last nk words stay live.
 template <int NR>
-__device__ __forceinline__ void expand_key_lane(const uint32_t *lds, const Bases &b,
-                                                const uint32_t (&key)[8],
-                                                uint32_t (&w)[4 * (NR + 1)]) {
+__device__ __forceinline__ void expand_key_quad(const uint32_t *lds, const Bases &b,
+                                                const uint32_t (&key)[8], uint32_t q,
+                                                uint32_t (&rk)[NR + 1]) {
     constexpr int nk = NR - 6;
+    uint32_t win[8];
 #pragma unroll
-    for (int i = 0; i < nk; ++i) w[i] = key[i];
+    for (int r = 0; r <= NR; ++r) rk[r] = 0;
+#pragma unroll
+    for (int i = 0; i < nk; ++i) {
+        win[i] = key[i];
+        rk[i / 4] = q == uint32_t(i & 3) ? win[i] : rk[i / 4];
+    }
     uint32_t rcon = 1;
 #pragma unroll
     for (int i = nk; i < 4 * (NR + 1); ++i) {
-        uint32_t t = w[i - 1];
+        uint32_t t = win[(i - 1) % nk];
         if (i % nk == 0) {
             t = sub_word_lane(lds, b, (t >> 8) | (t << 24)) ^ rcon;
             rcon = ((rcon << 1) ^ ((rcon >> 7) * 0x1Bu)) & 0xFFu;
         } else if (nk == 8 && i % nk == 4) {
             t = sub_word_lane(lds, b, t);
         }
-        w[i] = w[i - nk] ^ t;
+        win[i % nk] ^= t;
+        rk[i / 4] = q == uint32_t(i & 3) ? win[i % nk] : rk[i / 4];
     }
 }
 
 // CBC encryption (C_i = E_K(P_i ^ C_{i-1}), C_{-1} = IV, the inverse of Eq.
-// (2)) of a group of up to 64 messages of one key size, one message per lane,
-// each with its own key schedule in registers.  Blocks of a message are
-// sequential; lanes whose message has ended compute on and store nothing
-// (the group is sorted longest first).  Iteration i stores the previous block
-// and loads the next one before the rounds, so the only memory wait (for
-// block i, at the loop top) is on a load issued a whole block earlier.
+// (2)) of a group of up to 16 messages of one key size, four lanes per
+// message (lane q of a quad holds column q of the state and of every round
+// key).  Blocks of a message are sequential; quads whose message has ended
+// compute on and store nothing new (the group is sorted longest first).
+// Iteration i stores the previous block and loads the next one before the
+// rounds, so the only memory wait (for block i, at the loop top) is on a load
+// issued a whole block earlier.
 template <int NR>
 __device__ void cbc_encrypt_group(const uint32_t *lds, const Bases &b, const BatchParams &p,
                                   const Tile &tile, uint64_t n_max) {
     const uint32_t lane = threadIdx.x & 63u;
-    const bool active = lane < tile.n_blocks;
+    const uint32_t q = lane & 3u;
+    const bool active = (lane >> 2) < tile.n_blocks;
     DevMsg m{};
-    if (active) m = p.msgs[p.cbc_list[tile.msg + lane]];
-    uint32_t rk[4 * (NR + 1)];
+    if (active) m = p.msgs[p.cbc_list[tile.msg + (lane >> 2)]];
+    uint32_t rk[NR + 1];
     if (p.sched) {
         const uint32_t *w = p.sched + uint64_t(m.key_slot) * kSchedWords;
 #pragma unroll
-        for (int i = 0; i < 4 * (NR + 1); ++i) rk[i] = w[i];
+        for (int r = 0; r <= NR; ++r) rk[r] = w[4 * r + q];
     } else {
         const uint32_t *kp = reinterpret_cast<const uint32_t *>(p.keys + 32ull * m.key_slot);
         uint32_t key[8];
 #pragma unroll
         for (int i = 0; i < 8; ++i) key[i] = i < NR - 6 ? kp[i] : 0u;
-        expand_key_lane<NR>(lds, b, key, rk);
+        expand_key_quad<NR>(lds, b, key, q, rk);
     }
     const uint64_t n = active ? m.n_full : 0;
     const uint64_t last = n ? n - 1 : 0;
     // Every load and store is issued in every iteration (no branch), so the
-    // compiler can count them: a lane without a message reads and writes the
-    // dummy block; a lane whose message has ended rewrites its last block with
-    // the same value.
-    const uint4 *in = n ? reinterpret_cast<const uint4 *>(p.in + m.in_off) : p.cbc_dummy;
-    uint4 *out = n ? reinterpret_cast<uint4 *>(p.out + m.out_off) : p.cbc_dummy;
-    uint32_t c[4] = {m.nonce[0], m.nonce[1], m.nonce[2], m.ctr0};
-    uint4 pt = in[0];
+    // compiler can count them: a quad without a message reads and writes the
+    // dummy block; a quad whose message has ended rewrites its last block
+    // with the same value.
+    const uint32_t *dummy = reinterpret_cast<uint32_t *>(p.cbc_dummy);
+    const uint32_t *in = n ? reinterpret_cast<const uint32_t *>(p.in + m.in_off) : dummy;
+    uint32_t *out = n ? reinterpret_cast<uint32_t *>(p.out + m.out_off)
+                      : reinterpret_cast<uint32_t *>(p.cbc_dummy);
+    uint32_t c = q == 0 ? m.nonce[0] : q == 1 ? m.nonce[1] : q == 2 ? m.nonce[2] : m.ctr0;
+    uint32_t pt = in[q];
     for (uint64_t i = 0; i < n_max; ++i) {
-        uint32_t s[4] = {pt.x ^ c[0] ^ rk[0], pt.y ^ c[1] ^ rk[1], pt.z ^ c[2] ^ rk[2],
-                         pt.w ^ c[3] ^ rk[3]};
-        uint4 *dst = i == 0 ? p.cbc_dummy : out + (i - 1 < last ? i - 1 : last);
-        *dst = make_uint4(c[0], c[1], c[2], c[3]);
-        pt = in[i + 1 <= last ? i + 1 : last];
+        uint32_t s = pt ^ c ^ rk[0];
+        uint32_t *dst = i == 0 ? reinterpret_cast<uint32_t *>(p.cbc_dummy) + q
+                               : out + 4 * (i - 1 < last ? i - 1 : last) + q;
+        *dst = c;
+        pt = in[4 * (i + 1 <= last ? i + 1 : last) + q];
         // Compiler barrier: keeps the load of the next block issued here,
         // before the rounds, instead of sunk to the next iteration.
         asm volatile("" ::: "memory");
 #pragma unroll
-        for (int r = 1; r < NR; ++r) mid_round<false>(lds, b, s, &rk[4 * r]);
-        last_round_fwd(lds, b, s, &rk[4 * NR]);
+        for (int r = 1; r < NR; ++r) s = quad_round<false>(lds, b, s, rk[r]);
+        s = quad_round<true>(lds, b, s, rk[NR]);
         // A select, not a branch: c stays live across the rounds, so the
-        // registers the store above reads are not reused before it is done.
-#pragma unroll
-        for (int k = 0; k < 4; ++k) c[k] = i < n ? s[k] : c[k];
+        // register the store above reads is not reused before it is done.
+        c = i < n ? s : c;
     }
-    if (n) out[last] = make_uint4(c[0], c[1], c[2], c[3]);
+    if (n) out[4 * last + q] = c;
 }
 
 // The CBC-encryption launch: forward tables in LDS, then wave w of the grid
@@ -654,15 +692,15 @@ int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vec
     for (auto &t : tiles)
         std::stable_sort(t.begin(), t.end(),
                          [](const Tile &a, const Tile &b) { return a.n_blocks > b.n_blocks; });
-    // CBC-encrypt groups: per key size, longest first, 64 messages (lanes)
-    // per group; all groups longest first, since each runs its blocks one
+    // CBC-encrypt groups: per key size, longest first, 16 messages (four
+    // lanes each) per group; all groups longest first, since each runs its blocks one
     // after another.
     for (auto &v : cbc_enc) {
         std::stable_sort(v.begin(), v.end(), [&](uint32_t a, uint32_t b) {
             return dm[a].n_full > dm[b].n_full;
         });
-        for (size_t g = 0; g < v.size(); g += 64) {
-            const size_t n = std::min<size_t>(64, v.size() - g);
+        for (size_t g = 0; g < v.size(); g += kCbcGroupMsgs) {
+            const size_t n = std::min<size_t>(kCbcGroupMsgs, v.size() - g);
             cbc_groups.push_back(Tile{uint32_t(cbc_list.size()), uint32_t(n), dm[v[g]].n_full});
             cbc_list.insert(cbc_list.end(), v.begin() + long(g), v.begin() + long(g + n));
         }

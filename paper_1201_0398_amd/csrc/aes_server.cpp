@@ -24,6 +24,7 @@
 #include <thread>
 #include <vector>
 
+#include "aes_batch.h"
 #include "aes_internal.h"
 
 // ---- first-fit range allocator ---------------------------------------------------
