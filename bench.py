@@ -29,6 +29,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "AES-128 ECB/CTR GB/s at 1 GiB (% HBM roofline); batched GB/s; serve p50/p99"
 HBM_PEAK_GBS = 8000.0
+# LDS table reads per AES-128 block issued to the LDS by each kernel (CTR takes
+# 15 of its 148 from the scalar cache), and the LDS read peak: 256 CUs x 32
+# lanes per clock x 2.4 GHz.
+LDS_READS_PER_BLOCK = {"ecb_encrypt": 160, "ecb_decrypt": 160, "ctr_xcrypt": 133}
+LDS_PEAK_TREADS = 256 * 32 * 2.4e9 / 1e12
 GIB = 1 << 30
 
 
@@ -72,7 +77,7 @@ def parse():
                          "clock ramps up over tens of ms of sustained load)")
     ap.add_argument("--bytes", type=int, default=GIB)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample-bytes", type=int, default=96 << 20)
+    ap.add_argument("--cpu-sample-bytes", type=int, default=256 << 20)
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-reps", type=int, default=5)
@@ -420,7 +425,18 @@ def main() -> int:
                      "algorithmic_bytes": algo_bytes,
                      "note": "32 B of HBM per 16-B block; the kernel is bound by LDS table-read "
                              "issue (160 random reads per AES-128 block, 2 LDS cycles per wave64 "
-                             "read), see profiles/aes128_1gib_lds_valu_counters.md"},
+                             "read), see lds_roofline and "
+                             "profiles/aes128_1gib_lds_valu_counters.md"},
+        # The bound the kernel actually meets: LDS table reads, 32 lanes per
+        # clock per CU (a wave64 ds_read_b32 takes 2 cycles) at 256 CUs and the
+        # 2.4 GHz peak engine clock; 16 reads per round (paper section 2.1).
+        "lds_roofline": {"bound": "lds", "kernel": dominant,
+                         "achieved": round(LDS_READS_PER_BLOCK[dominant] * n_blocks /
+                                           (kern_ms[dominant] * 1e-3) / 1e12, 3),
+                         "peak": LDS_PEAK_TREADS, "unit": "T table reads/s",
+                         "frac": round(LDS_READS_PER_BLOCK[dominant] * n_blocks /
+                                       (kern_ms[dominant] * 1e-3) / 1e12 / LDS_PEAK_TREADS, 4),
+                         "reads_per_block": LDS_READS_PER_BLOCK[dominant]},
         "kernels": per_kernel,
     }
     if not args.no_batched:
