@@ -37,14 +37,18 @@ class SingleBuffer:
     data: np.ndarray    # uint8
     nonce: np.ndarray   # 12 bytes (CTR)
     ctr0: int
+    iv: np.ndarray | None = None   # 16 bytes (CBC, LE-128 CTR), where drawn
 
 
 def single_small(seed: int = 0, n_bytes: int = 1 << 20) -> SingleBuffer:
+    """Key, data, nonce, then (drawn last, so the earlier draws are unchanged
+    by it) a 16-byte IV for CBC and the LE-128 counter."""
     rng = np.random.default_rng(seed)
     key = _bytes(rng, 16)
     data = _bytes(rng, n_bytes)
     nonce = _bytes(rng, 12)
-    return SingleBuffer({128: key}, data, nonce, 1)
+    iv = _bytes(rng, 16)
+    return SingleBuffer({128: key}, data, nonce, 1, iv)
 
 
 def single_1gib(seed: int = 1, n_bytes: int = 1 << 30) -> SingleBuffer:

@@ -29,6 +29,10 @@ def main():
         "ecb128_decrypt_of_input_sha256": sha(oracle.ecb_decrypt(key, w.data)),
         "ecb128_roundtrip_ok": bool((oracle.ecb_decrypt(key, enc) == w.data).all()),
         "ctr128_sha256": sha(oracle.ctr(key, w.nonce, w.ctr0, w.data)),
+        "iv_sha256": sha(w.iv),
+        "ctr_le128_index0_0_sha256": sha(oracle.ctr_le128(key, w.iv, 0, w.data)),
+        "cbc128_encrypt_sha256": sha(oracle.cbc_encrypt(key, w.iv, w.data)),
+        "cbc128_decrypt_of_input_sha256": sha(oracle.cbc_decrypt(key, w.iv, w.data)),
     }
     with open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "oracle_digests.json"),
               "w") as f:

@@ -23,3 +23,7 @@ def test_oracle_digests_small_workload():
     assert _sha(oracle.ecb_encrypt(key, w.data)) == g["ecb128_encrypt_sha256"]
     assert _sha(oracle.ecb_decrypt(key, w.data)) == g["ecb128_decrypt_of_input_sha256"]
     assert _sha(oracle.ctr(key, w.nonce, w.ctr0, w.data)) == g["ctr128_sha256"]
+    assert _sha(w.iv) == g["iv_sha256"]
+    assert _sha(oracle.ctr_le128(key, w.iv, 0, w.data)) == g["ctr_le128_index0_0_sha256"]
+    assert _sha(oracle.cbc_encrypt(key, w.iv, w.data)) == g["cbc128_encrypt_sha256"]
+    assert _sha(oracle.cbc_decrypt(key, w.iv, w.data)) == g["cbc128_decrypt_of_input_sha256"]

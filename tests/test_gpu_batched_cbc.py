@@ -149,6 +149,33 @@ def test_cbc_round_trip_and_in_place(A, ctx):
         A.aesgpu_batch_free(dec)
 
 
+def test_cbc_encrypt_one_long_message_golden(A, ctx):
+    """One 1 MiB message (65,536 sequential blocks) of the seed-0 workload
+    through the CBC-encryption launch, against the stored oracle digest."""
+    import hashlib
+    import json
+    import os
+
+    import torch
+    from paper_1201_0398_amd import workloads
+    golden = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                          "oracle_digests.json")
+    w = workloads.single_small(seed=0)
+    n = w.data.size
+    keys = np.zeros(32, dtype=np.uint8)
+    keys[:16] = w.keys[128]
+    msgs = A.make_msgs([0], [0], [n], [0], [128], [A.AESGPU_MODE_CBC], [0],
+                       iv=np.asarray(w.iv).reshape(1, 16))
+    plan = A.aesgpu_batch_plan(ctx, msgs)
+    try:
+        d_out = torch.empty(n, dtype=torch.uint8, device="cuda")
+        A.aesgpu_batch_run(plan, to_dev(keys), 1, to_dev(w.data), d_out)
+        got = hashlib.sha256(from_dev(d_out).tobytes()).hexdigest()
+        assert got == json.load(open(golden))["cbc128_encrypt_sha256"]
+    finally:
+        A.aesgpu_batch_free(plan)
+
+
 def test_cbc_plan_validation(A, ctx):
     import ctypes
     msgs = A.make_msgs([0], [0], [24], [0], [128], [A.AESGPU_MODE_CBC], [0])

@@ -55,6 +55,25 @@ def test_small_workload_ecb128(A, ctx):
     assert hashlib.sha256(ct.tobytes()).hexdigest() == g["ecb128_encrypt_sha256"]
 
 
+def test_small_workload_paper_modes(A, ctx):
+    """The 1 MiB seed-0 workload through the paper's CTR counter and CBC
+    decryption, against the stored oracle digests."""
+    import torch
+    from paper_1201_0398_amd import workloads
+    log("case: 1 MiB LE-128 CTR and CBC decrypt seed 0")
+    w = workloads.single_small(seed=0)
+    key = w.keys[128]
+    k = A.aesgpu_expand_key(key)
+    g = json.load(open(GOLDEN))
+    d_in = to_dev(w.data)
+    d_out = torch.empty_like(d_in)
+    A.aesgpu_ctr_le128_xcrypt(ctx, k, w.iv, 0, d_in, d_out)
+    assert hashlib.sha256(from_dev(d_out).tobytes()).hexdigest() == g["ctr_le128_index0_0_sha256"]
+    A.aesgpu_cbc_decrypt(ctx, k, w.iv, d_in, d_out)
+    assert hashlib.sha256(from_dev(d_out).tobytes()).hexdigest() == \
+        g["cbc128_decrypt_of_input_sha256"]
+
+
 @pytest.mark.parametrize("kb", [16, 24, 32])
 @pytest.mark.parametrize("decrypt", [False, True], ids=["enc", "dec"])
 def test_ecb_sizes(A, ctx, kb, decrypt):
