@@ -175,10 +175,10 @@ typedef struct {
 
 #define AESGPU_BATCH_NO_GRAPH 1u /* enqueue the launches directly, no hipGraph */
 
-/* Launch shape of a batch; zero fields take the defaults (2 blocks per lane,
+/* Launch shape of a batch; zero fields take the defaults (4 blocks per lane,
  * 8192-block tiles).  tile_blocks must be a multiple of 64 * blocks_per_lane. */
 typedef struct {
-    uint32_t blocks_per_lane; /* 1 or 2 */
+    uint32_t blocks_per_lane; /* 1, 2 or 4 */
     uint32_t tile_blocks;
     uint32_t flags;           /* AESGPU_BATCH_* */
 } aesgpu_batch_config;
@@ -332,7 +332,7 @@ typedef struct aesgpu_server aesgpu_server;
 typedef struct {
     uint64_t arena_bytes;        /* device memory for request outputs (multiple of 256) */
     uint32_t n_streams;          /* batches in flight at once (0 = 4, at most 8) */
-    uint32_t blocks_per_lane;    /* 1 or 2 (0 = 2) */
+    uint32_t blocks_per_lane;    /* 1, 2 or 4 (0 = 2) */
     uint32_t tile_blocks;        /* 0 = chosen per batch (about two tiles per wave slot) */
     uint32_t max_batch_requests; /* 0 = no limit */
     uint64_t max_batch_bytes;    /* 0 = no limit */

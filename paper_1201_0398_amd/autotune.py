@@ -20,7 +20,7 @@ import math
 import os
 from dataclasses import dataclass
 
-DEFAULT_CANDIDATES = [(bpl, tile) for bpl in (1, 2) for tile in (1024, 2048, 4096, 8192)]
+DEFAULT_CANDIDATES = [(bpl, tile) for bpl in (1, 2, 4) for tile in (1024, 2048, 4096, 8192)]
 
 
 def cache_path() -> str:

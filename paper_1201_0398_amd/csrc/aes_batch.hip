@@ -630,7 +630,7 @@ int enqueue_t(const BatchLaunch &L, hipStream_t s) {
 }  // namespace
 
 int enqueue_batch(const BatchLaunch &L, hipStream_t s) {
-    return L.bpl == 1 ? enqueue_t<1>(L, s) : enqueue_t<2>(L, s);
+    return L.bpl == 1 ? enqueue_t<1>(L, s) : L.bpl == 2 ? enqueue_t<2>(L, s) : enqueue_t<4>(L, s);
 }
 
 int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vector<DevMsg> &dm,
@@ -715,7 +715,7 @@ int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vec
 using namespace aesgpu;
 
 namespace {
-constexpr uint32_t kDefaultBpl = 2;
+constexpr uint32_t kDefaultBpl = 4;
 constexpr uint32_t kDefaultTileBlocks = 8192;
 }  // namespace
 
@@ -793,7 +793,7 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
         if (cfg->tile_blocks) tile_blocks = cfg->tile_blocks;
         use_graph = !(cfg->flags & AESGPU_BATCH_NO_GRAPH);
     }
-    if (bpl != 1 && bpl != 2) return AESGPU_EINVAL;
+    if (bpl != 1 && bpl != 2 && bpl != 4) return AESGPU_EINVAL;
     if (tile_blocks % (64u * bpl) != 0 || tile_blocks > (1u << 24)) return AESGPU_EINVAL;
 
     std::vector<DevMsg> dm;

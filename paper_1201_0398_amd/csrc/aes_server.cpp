@@ -399,7 +399,8 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
     if (!c.n_streams) c.n_streams = 4;
     if (!c.blocks_per_lane) c.blocks_per_lane = 2;
     if (!c.max_queued) c.max_queued = 1u << 20;
-    if (c.n_streams > 8 || (c.blocks_per_lane != 1 && c.blocks_per_lane != 2) ||
+    if (c.n_streams > 8 ||
+        (c.blocks_per_lane != 1 && c.blocks_per_lane != 2 && c.blocks_per_lane != 4) ||
         c.tile_blocks % (64u * c.blocks_per_lane) || c.arena_bytes < 256 || c.arena_bytes % 256)
         return AESGPU_EINVAL;
     // Expand every pool key on the host (encryption and decryption schedules).

@@ -62,7 +62,7 @@ def _plan(A, ctx, b, **kw):
     return A.aesgpu_batch_plan(ctx, msgs, **kw)
 
 
-@pytest.mark.parametrize("bpl,tile", [(1, 2048), (2, 128), (2, 8192), (1, 64)])
+@pytest.mark.parametrize("bpl,tile", [(1, 2048), (2, 128), (2, 8192), (1, 64), (4, 256), (4, 8192)])
 def test_mixed_batch_matches_oracle(A, ctx, bpl, tile):
     import torch
     rng = np.random.default_rng(30 + bpl + tile)

@@ -95,7 +95,7 @@ def _run_and_check(A, ctx, b, **kw):
         A.aesgpu_batch_free(plan)
 
 
-@pytest.mark.parametrize("bpl,graph", [(1, True), (2, True), (2, False)])
+@pytest.mark.parametrize("bpl,graph", [(1, True), (2, True), (2, False), (4, True)])
 def test_mixed_batch_with_cbc(A, ctx, bpl, graph):
     rng = np.random.default_rng(9000 + bpl + 10 * graph)
     m = 600
