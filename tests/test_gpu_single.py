@@ -294,3 +294,47 @@ def test_side_stream(A, ctx):
         A.aesgpu_ecb_encrypt(ctx, k, d_in, d_out, stream=s)
     s.synchronize()
     assert np.array_equal(from_dev(d_out), oracle.ecb_encrypt(key, data))
+
+
+def test_threads_and_streams_share_one_context(A, ctx):
+    """Four host threads, each with its own stream, key size and mode, issue
+    calls on one context at the same time (the context is immutable after
+    creation); every output matches the oracle."""
+    import threading
+
+    import torch
+    rng = np.random.default_rng(10)
+    jobs = []
+    for t in range(4):
+        kb = (16, 24, 32, 16)[t]
+        key = rng.integers(0, 256, kb, dtype=np.uint8)
+        data = rng.integers(0, 256, 16 * (20000 + 777 * t), dtype=np.uint8)
+        nonce = rng.integers(0, 256, 12, dtype=np.uint8)
+        jobs.append(dict(key=key, data=data, nonce=nonce, d_in=to_dev(data)))
+    torch.cuda.synchronize()
+    errors = []
+
+    def work(t, job):
+        try:
+            s = torch.cuda.Stream()
+            k = A.aesgpu_expand_key(job["key"])
+            d_a = torch.empty_like(job["d_in"])
+            d_b = torch.empty_like(job["d_in"])
+            for _ in range(5):
+                A.aesgpu_ecb_encrypt(ctx, k, job["d_in"], d_a, stream=s)
+                A.aesgpu_ecb_decrypt(ctx, k, d_a, d_b, stream=s)
+                A.aesgpu_ctr_xcrypt(ctx, k, job["nonce"], 7, d_b, d_b, stream=s)
+            s.synchronize()
+            job["enc"], job["ctr"] = from_dev(d_a), from_dev(d_b)
+        except Exception as e:  # noqa: BLE001
+            errors.append((t, e))
+
+    threads = [threading.Thread(target=work, args=(t, j)) for t, j in enumerate(jobs)]
+    for th in threads:
+        th.start()
+    for th in threads:
+        th.join()
+    assert not errors, errors
+    for j in jobs:
+        assert np.array_equal(j["enc"], oracle.ecb_encrypt(j["key"], j["data"]))
+        assert np.array_equal(j["ctr"], oracle.ctr(j["key"], j["nonce"], 7, j["data"]))
