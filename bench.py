@@ -131,6 +131,24 @@ def single_rates(torch, A, ctx, w, d_in, d_out, reps: int = 3) -> dict:
     return rates
 
 
+def size_sweep(torch, A, ctx, w, d_in, d_out) -> list:
+    """AES-128 ECB encryption of device-resident buffers from 16 KiB to 1 GiB:
+    the per-call time where launch and staging dominate (small data, the
+    regime the paper's section 3.1 discusses) up to the streaming rate.  Each
+    size first runs for at least 20 ms untimed (the clock drops during runs
+    of tiny calls) and is then timed over at least 20 ms of calls."""
+    k = A.aesgpu_expand_key(bytes(w.keys[128]))
+    rows = []
+    for n in [1 << 14, 1 << 16, 1 << 18, 1 << 20, 1 << 22, 1 << 24, 1 << 26, 1 << 28, 1 << 30]:
+        call = lambda: A.aesgpu_ecb_encrypt(ctx, k, d_in, d_out, n // 16)  # noqa: E731
+        t_one = time_call(torch, call, 1)
+        reps = max(5, int(0.02 / t_one) + 1)
+        time_call(torch, call, reps)              # warm-up at this size
+        t = time_call(torch, call, reps)
+        rows.append({"bytes": n, "us": round(t * 1e6, 2), "GB_s": round(n / t / 1e9, 1)})
+    return rows
+
+
 def batched_bench(torch, A, ctx, rates: dict, reps: int) -> dict:
     """The 65,536-message batch (seed 3), encrypt direction, graph replays."""
     import numpy as np
@@ -442,6 +460,7 @@ def main() -> int:
     if not args.no_batched:
         rates = single_rates(torch, A, ctx, w, d_in, d_ct)
         out["single_buffer_GB_s"] = {f"aes{b}_{m}": round(v / 1e9, 1) for (b, m), v in rates.items()}
+        out["single_buffer_sizes_aes128_ecb_enc"] = size_sweep(torch, A, ctx, w, d_in, d_ct)
         del d_pt, d_ctr
         out["batched"] = batched_bench(torch, A, ctx, rates, args.batched_reps)
     if not args.no_serving:
