@@ -125,14 +125,14 @@ __device__ __forceinline__ void last_round_inv(const uint32_t *lds, const Bases 
 }
 
 // Copies the table set into the LDS image.  Loads are issued in groups of
-// eight before their LDS writes, so the staging costs a few L2 round trips
-// instead of one per word, with few registers live.  Needs blockDim.x == WG.
-template <bool kInv, int WG = kWG>
+// kGroup before their LDS writes, so the staging costs a few L2 round trips
+// instead of one per word; a wave's loads hit two distinct words (every lane
+// of a wave writes copies of the same table entry).  Needs blockDim.x == WG.
+template <bool kInv, int WG = kWG, int kGroup = 16>
 __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ g) {
-    static_assert(kFwdWords % (WG * 8) == 0 && kInvSWords % WG == 0, "workgroup size");
+    static_assert(kFwdWords % (WG * kGroup) == 0 && kInvSWords % WG == 0, "workgroup size");
     const uint32_t *src = g + (kInv ? kTd : kTe);
     constexpr int kPer = kFwdWords / WG;
-    constexpr int kGroup = 8;
 #pragma unroll 1
     for (int k0 = 0; k0 < kPer; k0 += kGroup) {
         uint32_t v[kGroup];

@@ -25,7 +25,8 @@
 //    lookups per block for the first two rounds.
 //  * 1024 threads per workgroup and one workgroup per CU (the tables take the
 //    whole LDS); the grid is at most one workgroup per CU and strides over
-//    tiles of 1024 * BPL blocks.
+//    tiles of 1024 * BPL blocks.  BPL is 4 when every CU gets a full tile and
+//    smaller for smaller buffers (every slot of a tile is computed).
 #include <hip/hip_runtime.h>
 
 #include <cstdlib>
@@ -155,8 +156,6 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kCtr = (OP == Op::kCtrBe32 || OP == Op::kCtrLe128);
     constexpr bool kLM = kCtr || OP == Op::kCbcDec;   // lane-major tiles
     __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords];
-    stage_tables<kInv>(lds, p.tables);
-    const Bases b = lane_bases();
 
     // The loop covers the whole blocks; a CTR tail is finished after it.
     const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
@@ -165,6 +164,8 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     const uint32_t wave_first = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
     // The blocks of the next tile are loaded while the current one is
     // computed, so HBM latency overlaps the rounds even at low occupancy.
+    // The first tile's loads are issued before the tables are staged, so their
+    // HBM latency overlaps the staging.
     uint4 next[BPL];
     uint4 next_prev = make_uint4(0, 0, 0, 0);   // CBC only
     TileView view = tile_view(p.in, p.out, uint64_t(blockIdx.x) * tile, p.n_full, p.voff, tile);
@@ -172,6 +173,8 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     if constexpr (OP == Op::kCbcDec)
         next_prev = load_wave_prev<BPL>(p.in, uint64_t(blockIdx.x) * tile, wave_first, p.n_full,
                                         uint32_t(tile));
+    stage_tables<kInv>(lds, p.tables);
+    const Bases b = lane_bases();
     // In the loop a tile's loads are followed by the previous tile's stores,
     // and the loop top waits for the loads only.  These stores have an empty
     // range and write nothing; they give the loop entry the same order, so
@@ -368,7 +371,18 @@ int launch_op(const Params &p, uint32_t nr, int n_cu, hipStream_t stream) {
         const char *e = std::getenv("AESGPU_FORCE_BPL");
         return e ? std::atoi(e) : 0;
     }();
-    switch (forced) {
+    int bpl = forced;
+    if (bpl != 1 && bpl != 2 && bpl != 4) {
+        // Every lane computes all its slots, empty or not, so a tile only
+        // pays off when it is full: 4 blocks per lane once every CU gets a
+        // whole tile of 4096 blocks, 1 block per lane for small buffers (a
+        // 16 KiB call then costs one 1024-block tile instead of a 4096-slot
+        // one, a quarter of the table reads).
+        const uint64_t blocks = p.n_full + (p.tail ? 1 : 0);
+        const uint64_t cus = uint64_t(n_cu);
+        bpl = blocks >= cus * kWG * 4 ? 4 : blocks >= cus * kWG * 2 ? 2 : 1;
+    }
+    switch (bpl) {
         case 1: return launch_nr<OP, 1>(p, nr, n_cu, stream);
         case 2: return launch_nr<OP, 2>(p, nr, n_cu, stream);
         default: return launch_nr<OP, 4>(p, nr, n_cu, stream);
