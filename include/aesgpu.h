@@ -337,8 +337,12 @@ typedef struct {
     uint32_t max_batch_requests; /* 0 = no limit */
     uint64_t max_batch_bytes;    /* 0 = no limit */
     uint32_t max_queued;         /* waiting requests before EAGAIN (0 = 2^20) */
-    uint32_t reserved;
+    uint32_t direct_requests;    /* batches of at most this many requests run as one
+                                    single-buffer launch per request (0 = 4, at most 16;
+                                    AESGPU_SERVER_NO_DIRECT: always the batched kernel) */
 } aesgpu_server_config;
+
+#define AESGPU_SERVER_NO_DIRECT 0xFFFFFFFFu
 
 /* A finished request.  d_out points into the server's arena and stays valid
  * until aesgpu_server_release().  Times are seconds on the server clock
@@ -383,7 +387,10 @@ typedef struct {
  * are ECB (the paper's section 3 parallel mode) in either direction.  Each
  * dispatch launches all admitted requests as one batched run (the persistent
  * launch of aesgpu_batch_run, with resident schedules instead of device key
- * expansion).  Errors: EINVAL, EKEYLEN, ENOMEM, EHIP.
+ * expansion, after an upload of the batch's descriptors); a batch of at most
+ * direct_requests requests instead runs as one single-buffer kernel per
+ * request with the round keys as kernel arguments, which saves the upload.
+ * Errors: EINVAL, EKEYLEN, ENOMEM, EHIP.
  */
 int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *key_bits,
                          size_t n_keys, const aesgpu_server_config *cfg, aesgpu_server **out);

@@ -5,7 +5,8 @@
 // as long as their output fits in a device arena (first-fit ranges), and
 // whenever one of its streams is idle it launches every admitted request as
 // one batched run (the persistent kernel of the batched path, reading the
-// pool's key schedules that stay resident on the device).  Requests that
+// pool's key schedules that stay resident on the device), or, for a batch of
+// only a few requests, as one single-buffer launch per request.  Requests that
 // arrive while earlier batches are still on the GPU are admitted and launched
 // on the next free stream, so batches overlap on the device.  Completion is
 // observed through one event per launch; outputs stay in the arena until the
@@ -165,6 +166,7 @@ struct aesgpu_server {
     aesgpu_server_config cfg{};
     size_t n_keys = 0;
     std::vector<uint16_t> key_bits;
+    std::vector<uint32_t> h_sched;  // host copy of the schedules (direct launches)
     uint32_t *d_sched = nullptr;
     uint8_t *d_arena = nullptr;
     aesgpu_arena arena;
@@ -204,6 +206,25 @@ bool ensure(void **p, size_t *cap, size_t need, bool pinned) {
 // Launches the requests in slot.reqs; returns an AESGPU status.
 int launch_slot(aesgpu_server *s, Slot &slot) {
     const size_t m = slot.reqs.size();
+    if (s->cfg.direct_requests != AESGPU_SERVER_NO_DIRECT && m <= s->cfg.direct_requests) {
+        // A few requests: the single-buffer kernel, round keys as kernel
+        // arguments.  Nothing is copied to the device first, so a small batch
+        // costs its launches only, and each request gets the whole chip.
+        for (const Req &r : slot.reqs) {
+            const bool dec = r.dir == AESGPU_DIR_DECRYPT;
+            LaunchArgs a{};
+            a.op = dec ? Op::kEcbDec : Op::kEcbEnc;
+            a.nr = s->key_bits[r.key] / 32u + 6u;
+            a.in = r.in;
+            a.out = s->d_arena + r.out_off;
+            a.n_bytes = r.n;
+            a.rk = reinterpret_cast<const RoundKeys *>(
+                s->h_sched.data() + size_t(r.key) * kSchedWords + (dec ? 64 : 0));
+            const int st = launch(s->ctx->d_tables, s->ctx->n_cu, a, slot.stream);
+            if (st != AESGPU_OK) return st;
+        }
+        return hipEventRecord(slot.done, slot.stream) == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
+    }
     std::vector<aesgpu_msg> msgs(m);
     for (size_t i = 0; i < m; ++i) {
         const Req &r = slot.reqs[i];
@@ -399,9 +420,11 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
     if (!c.n_streams) c.n_streams = 4;
     if (!c.blocks_per_lane) c.blocks_per_lane = 2;
     if (!c.max_queued) c.max_queued = 1u << 20;
+    if (!c.direct_requests) c.direct_requests = 4;
     if (c.n_streams > 8 ||
         (c.blocks_per_lane != 1 && c.blocks_per_lane != 2 && c.blocks_per_lane != 4) ||
-        c.tile_blocks % (64u * c.blocks_per_lane) || c.arena_bytes < 256 || c.arena_bytes % 256)
+        c.tile_blocks % (64u * c.blocks_per_lane) || c.arena_bytes < 256 || c.arena_bytes % 256 ||
+        (c.direct_requests > 16 && c.direct_requests != AESGPU_SERVER_NO_DIRECT))
         return AESGPU_EINVAL;
     // Expand every pool key on the host (encryption and decryption schedules).
     std::vector<uint32_t> sched(n_keys * kSchedWords, 0u);
@@ -418,6 +441,7 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
     s->cfg = c;
     s->n_keys = n_keys;
     s->key_bits.assign(key_bits, key_bits + n_keys);
+    s->h_sched = sched;
     s->arena.capacity = c.arena_bytes;
     s->arena.granule = 256;
     s->arena.free_ranges.emplace(0, c.arena_bytes);

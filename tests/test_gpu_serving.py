@@ -59,15 +59,20 @@ def _drain(A, server, want, copies):
         time.sleep(0.0005)
 
 
-def test_in_mix_and_alone_match_oracle(A, ctx, pool):
+@pytest.mark.parametrize("direct", ["default", "never"])
+def test_in_mix_and_alone_match_oracle(A, ctx, pool, direct):
+    """Alone, a request is a batch of one: a single-buffer launch by default,
+    the batched kernel when direct launches are off."""
     import torch
     tr = pool
     n = tr.sizes.size
     src = torch.from_numpy(tr.source.copy()).to("cuda")
     base = src.data_ptr()
-    server = A.aesgpu_server_create(ctx, tr.pool_keys, tr.pool_bits, arena_bytes=64 << 20)
+    server = A.aesgpu_server_create(
+        ctx, tr.pool_keys, tr.pool_bits, arena_bytes=64 << 20,
+        direct_requests=A.AESGPU_SERVER_NO_DIRECT if direct == "never" else 0)
     try:
-        log(f"case: {n} requests submitted at once (in the mix)")
+        log(f"case: {n} requests submitted at once (in the mix), direct={direct}")
         mix = {}
         for j in range(n):
             A.aesgpu_server_submit(server, j, int(tr.dirs[j]), int(tr.key_ids[j]),
@@ -89,13 +94,17 @@ def test_in_mix_and_alone_match_oracle(A, ctx, pool):
         A.aesgpu_server_destroy(server)
 
 
-def test_tiny_arena_forces_reuse(A, ctx, pool):
+@pytest.mark.parametrize("direct", [0, 16])
+def test_tiny_arena_forces_reuse(A, ctx, pool, direct):
+    """Batches of up to 7 requests in a 128 KiB arena; with direct=16 every
+    batch runs as single-buffer launches, one per request."""
     import torch
     tr = pool
     src = torch.from_numpy(tr.source.copy()).to("cuda")
     base = src.data_ptr()
+    log(f"case: tiny arena, direct={direct}")
     server = A.aesgpu_server_create(ctx, tr.pool_keys, tr.pool_bits, arena_bytes=1 << 17,
-                                    max_batch_requests=7)
+                                    max_batch_requests=7, direct_requests=direct)
     try:
         outs = {}
         n = 300
@@ -117,6 +126,27 @@ def test_tiny_arena_forces_reuse(A, ctx, pool):
         assert A.aesgpu_server_submit(server, 0, 0, 0, base, 24, check=False) == A.AESGPU_EINVAL
     finally:
         A.aesgpu_server_destroy(server)
+
+
+def test_server_config_errors(A, ctx, pool):
+    import ctypes
+    tr = pool
+    L = A.lib()
+    out = ctypes.c_void_p()
+    keys = np.ascontiguousarray(tr.pool_keys)
+    bits = np.ascontiguousarray(tr.pool_bits, dtype=np.uint16)
+    for bad in [dict(direct_requests=17), dict(n_streams=9), dict(blocks_per_lane=3),
+                dict(arena_bytes=100), dict(tile_blocks=100)]:
+        kw = dict(arena_bytes=1 << 20)
+        kw.update(bad)
+        cfg = A.aesgpu_server_config(kw.pop("arena_bytes"), kw.get("n_streams", 0),
+                                     kw.get("blocks_per_lane", 0), kw.get("tile_blocks", 0),
+                                     0, 0, 0, kw.get("direct_requests", 0))
+        st = L.aesgpu_server_create(ctx, keys.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
+                                    bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),
+                                    bits.size, ctypes.byref(cfg), ctypes.byref(out))
+        assert st == A.AESGPU_EINVAL, bad
+        assert not out.value
 
 
 def test_replay_poisson_trace(A, ctx, pool):
