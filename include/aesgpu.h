@@ -274,9 +274,11 @@ typedef struct aesgpu_pipeline aesgpu_pipeline;
 /*
  * The data path of the paper's section 3 (upload, encrypt, read back), as a
  * pipeline: chunk_bytes (a multiple of 16; 0 = 8 MiB) per chunk and n_slots
- * chunks in flight (1..16; 0 = 3), each slot with its own stream, two device
- * chunk buffers and two pinned staging buffers, allocated here.  flags: 0 or
- * AESGPU_PIPELINE_COPY.  Errors: EINVAL, ENOMEM, EHIP.
+ * chunks in flight (1..16; 0 = 3), each slot with its own stream and two
+ * pinned, mapped staging buffers (plus two device chunk buffers with
+ * AESGPU_PIPELINE_COPY), allocated here, and a few host threads that split
+ * the staging copies.  flags: 0 or AESGPU_PIPELINE_COPY.  Errors: EINVAL,
+ * ENOMEM, EHIP.
  */
 int aesgpu_pipeline_create(aesgpu_ctx *ctx, size_t chunk_bytes, int n_slots, uint32_t flags,
                            aesgpu_pipeline **out);
@@ -286,11 +288,14 @@ int aesgpu_pipeline_create(aesgpu_ctx *ctx, size_t chunk_bytes, int n_slots, uin
  * returns when the output is complete.  When both ranges lie in
  * aesgpu_host_alloc() allocations (and AESGPU_PIPELINE_COPY is not set), the
  * library's kernel for `op` reads and writes them directly over the host link
- * (zero copy, both directions at once).  Otherwise each chunk is copied to
- * the device, processed (chunk k continues the counter or the CBC chain of
- * chunk k - 1) and copied back, on its slot's stream, so transfers overlap
- * kernels; aesgpu_host_alloc() memory is then moved by DMA and other memory
- * through the pinned staging buffers (a CPU copy per chunk).
+ * (zero copy, both directions at once), in one launch.  Otherwise the buffer
+ * runs in chunks, one per slot and stream at a time (chunk k continues the
+ * counter or the CBC chain of chunk k - 1).  Without AESGPU_PIPELINE_COPY
+ * the kernel still works on host memory: an aligned aesgpu_host_alloc()
+ * range directly, other memory through the slot's staging buffers (a CPU
+ * copy in before the kernel and out after it).  With AESGPU_PIPELINE_COPY
+ * each chunk is copied to the device by DMA, processed and copied back
+ * (pageable memory through the staging buffers).
  * h_in == h_out runs in place (not for CBC); other overlap is EINVAL.  ECB
  * and CBC take whole blocks.  Calls on one pipeline must not overlap in time.
  * Errors: EINVAL, ECTR_OVERFLOW, EHIP.

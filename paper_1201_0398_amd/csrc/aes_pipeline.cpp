@@ -4,21 +4,25 @@
 // mapped into a texture, drawn, and the output read back, and its section 3.1
 // finds the GPU slower than the CPU for small data because of that transfer
 // cost.  This is the same data path done as a pipeline: the buffer is cut
-// into chunks, and each chunk's host-to-device copy, kernel and device-to-host
-// copy run on one of several streams, so the copies of one chunk overlap the
-// kernels and copies of the others.  Pageable host memory goes through pinned
-// staging buffers with a CPU copy, which overlaps the device work of the
-// other slots.  Host buffers allocated with aesgpu_host_alloc() (pinned and
-// mapped into the device's address space) need no staging: by default the
-// kernel then reads its input from and writes its output to host memory
-// directly over PCIe (zero copy), so both directions of the link are busy at
-// once; with AESGPU_PIPELINE_COPY they are moved by DMA copies instead.
+// into chunks that run on several streams, so the transfers of one chunk
+// overlap the device work of the others.  Host buffers allocated with
+// aesgpu_host_alloc() (pinned and mapped into the device's address space)
+// need no staging: by default the kernel reads its input from and writes its
+// output to host memory directly over PCIe (zero copy), so both directions of
+// the link are busy at once.  Pageable host memory goes through pinned,
+// mapped staging buffers: a CPU copy, split over a few threads, fills a
+// chunk's input staging buffer, the kernel reads it and writes the output
+// staging buffer over the link, and a CPU copy moves that to the caller while
+// the other slots' kernels run.  With AESGPU_PIPELINE_COPY each chunk is
+// instead moved to device buffers and back by DMA copies on its stream.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <cstring>
 #include <map>
 #include <mutex>
+#include <thread>
 #include <vector>
 
 #include "aes_internal.h"
@@ -61,11 +65,94 @@ bool ranges_overlap(const void *a, const void *b, size_t n) {
 struct Slot {
     hipStream_t stream = nullptr;
     hipEvent_t done = nullptr;
-    void *d_in = nullptr, *d_out = nullptr;
+    void *d_in = nullptr, *d_out = nullptr;   // device chunk buffers (DMA copies)
     void *h_in = nullptr, *h_out = nullptr;   // pinned staging
+    void *hd_in = nullptr, *hd_out = nullptr; // the staging buffers' device addresses
     bool busy = false;
     uint64_t off = 0, len = 0;                // chunk in flight
     bool staged_out = false;
+};
+
+// Host copies split over a few threads: one thread's memcpy reaches only a
+// part of the host's memory bandwidth, and the staging copies bound the
+// pageable path.  The calling thread copies one part itself.  Not
+// reentrant: one copy at a time.
+class CopyPool {
+  public:
+    static constexpr int kThreads = 4;            // including the caller
+    static constexpr size_t kMinSplit = 1u << 20;  // smaller copies stay on one thread
+
+    CopyPool() {
+        try {
+            for (int i = 1; i < kThreads; ++i) workers_.emplace_back([this, i] { work(i); });
+        } catch (...) {
+            shutdown();  // no threads: every copy runs on the caller
+        }
+    }
+    ~CopyPool() { shutdown(); }
+
+    void copy(void *dst, const void *src, size_t n) {
+        if (n < kMinSplit || workers_.empty()) {
+            std::memcpy(dst, src, n);
+            return;
+        }
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            dst_ = static_cast<char *>(dst);
+            src_ = static_cast<const char *>(src);
+            n_ = n;
+            pending_ = int(workers_.size());
+            ++gen_;
+        }
+        cv_.notify_all();
+        part(0);
+        std::unique_lock<std::mutex> lk(mu_);
+        done_cv_.wait(lk, [&] { return pending_ == 0; });
+    }
+
+  private:
+    void shutdown() {
+        {
+            std::lock_guard<std::mutex> lk(mu_);
+            stop_ = true;
+        }
+        cv_.notify_all();
+        for (std::thread &t : workers_) t.join();
+        workers_.clear();
+    }
+
+    // Part i of the current copy: kThreads pieces, cut at 4 KiB multiples.
+    void part(int i) {
+        const size_t piece = (n_ / kThreads + 4095) & ~size_t(4095);
+        const size_t a = std::min(n_, piece * size_t(i));
+        const size_t b = i == kThreads - 1 ? n_ : std::min(n_, a + piece);
+        if (b > a) std::memcpy(dst_ + a, src_ + a, b - a);
+    }
+
+    void work(int i) {
+        uint64_t seen = 0;
+        for (;;) {
+            {
+                std::unique_lock<std::mutex> lk(mu_);
+                cv_.wait(lk, [&] { return stop_ || gen_ != seen; });
+                if (stop_) return;
+                seen = gen_;
+            }
+            part(i);
+            std::lock_guard<std::mutex> lk(mu_);
+            if (--pending_ == 0) done_cv_.notify_one();
+        }
+    }
+
+    std::vector<std::thread> workers_;
+    std::mutex mu_;
+    std::condition_variable cv_, done_cv_;
+    uint64_t gen_ = 0;
+    int pending_ = 0;
+    bool stop_ = false;
+    char *dst_ = nullptr;
+    const char *src_ = nullptr;
+    size_t n_ = 0;
 };
 
 }  // namespace
@@ -76,6 +163,7 @@ struct aesgpu_pipeline {
     size_t chunk = 0;
     uint32_t flags = 0;
     std::vector<Slot> slots;
+    CopyPool copies;
 };
 
 namespace {
@@ -94,12 +182,20 @@ void free_slots(aesgpu_pipeline *pl) {
 }
 
 // Waits for a slot's chunk and copies its staged output to the caller.
-int finish(Slot &s, uint8_t *h_out) {
+int finish(aesgpu_pipeline *pl, Slot &s, uint8_t *h_out) {
     if (!s.busy) return AESGPU_OK;
     s.busy = false;
     if (hipEventSynchronize(s.done) != hipSuccess) return AESGPU_EHIP;
-    if (s.staged_out) std::memcpy(h_out + s.off, s.h_out, s.len);
+    if (s.staged_out) pl->copies.copy(h_out + s.off, s.h_out, s.len);
     return AESGPU_OK;
+}
+
+// Pinned, mapped host memory and its device address.
+bool alloc_mapped(size_t n, void **host, void **dev) {
+    if (hipHostMalloc(host, n, hipHostMallocMapped | hipHostMallocPortable) != hipSuccess ||
+        !*host)
+        return false;
+    return hipHostGetDevicePointer(dev, *host, 0) == hipSuccess && *dev;
 }
 
 // The device call for one chunk of `op` starting at byte `off` of the run.
@@ -170,8 +266,12 @@ int aesgpu_pipeline_create(aesgpu_ctx *ctx, size_t chunk_bytes, int n_slots, uin
     if (chunk_bytes == 0) chunk_bytes = kDefaultChunk;
     if (n_slots == 0) n_slots = kDefaultSlots;
     if (chunk_bytes % 16 != 0 || n_slots < 1 || n_slots > kMaxSlots) return AESGPU_EINVAL;
-    auto *pl = new (std::nothrow) aesgpu_pipeline;
-    if (!pl) return AESGPU_ENOMEM;
+    aesgpu_pipeline *pl = nullptr;
+    try {
+        pl = new aesgpu_pipeline;
+    } catch (...) {
+        return AESGPU_ENOMEM;
+    }
     pl->ctx = ctx;
     pl->device = ctx->device;
     pl->chunk = chunk_bytes;
@@ -184,10 +284,11 @@ int aesgpu_pipeline_create(aesgpu_ctx *ctx, size_t chunk_bytes, int n_slots, uin
         if (hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking) != hipSuccess ||
             hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
             st = AESGPU_EHIP;
-        } else if (hipMalloc(&s.d_in, chunk_bytes) != hipSuccess ||
-                   hipMalloc(&s.d_out, chunk_bytes) != hipSuccess ||
-                   hipHostMalloc(&s.h_in, chunk_bytes, hipHostMallocDefault) != hipSuccess ||
-                   hipHostMalloc(&s.h_out, chunk_bytes, hipHostMallocDefault) != hipSuccess) {
+        } else if (!alloc_mapped(chunk_bytes, &s.h_in, &s.hd_in) ||
+                   !alloc_mapped(chunk_bytes, &s.h_out, &s.hd_out) ||
+                   ((flags & AESGPU_PIPELINE_COPY) &&
+                    (hipMalloc(&s.d_in, chunk_bytes) != hipSuccess ||
+                     hipMalloc(&s.d_out, chunk_bytes) != hipSuccess))) {
             st = AESGPU_ENOMEM;
         }
     }
@@ -234,28 +335,56 @@ int aesgpu_pipeline_run(aesgpu_pipeline *pl, const aesgpu_key *key, const aesgpu
         return zs;
     }
     const size_t n_slots = pl->slots.size();
+    const bool dma = pl->flags & AESGPU_PIPELINE_COPY;
+    // Without DMA copies the kernel works on host memory: the caller's own
+    // pinned range where it is 16-byte aligned (chunk offsets keep that),
+    // else the slot's staging buffer.
+    const bool direct_in = !dma && pinned_in && dev_in % 16 == 0;
+    const bool direct_out = !dma && pinned_out && dev_out % 16 == 0;
     int st = AESGPU_OK;
     uint64_t c = 0;
     for (uint64_t off = 0; off < n_bytes && st == AESGPU_OK; off += pl->chunk, ++c) {
         Slot &s = pl->slots[c % n_slots];
-        st = finish(s, dst);
+        st = finish(pl, s, dst);
         if (st != AESGPU_OK) break;
         const uint64_t len = std::min<uint64_t>(pl->chunk, n_bytes - off);
-        const void *from = src + off;
-        if (!pinned_in) {
-            std::memcpy(s.h_in, src + off, len);
-            from = s.h_in;
+        const void *k_in;
+        void *k_out;
+        if (dma) {
+            const void *from = src + off;
+            if (!pinned_in) {
+                pl->copies.copy(s.h_in, src + off, len);
+                from = s.h_in;
+            }
+            if (hipMemcpyAsync(s.d_in, from, len, hipMemcpyHostToDevice, s.stream) !=
+                hipSuccess) {
+                st = AESGPU_EHIP;
+                break;
+            }
+            k_in = s.d_in;
+            k_out = s.d_out;
+        } else {
+            if (direct_in) {
+                k_in = reinterpret_cast<const void *>(dev_in + off);
+            } else {
+                pl->copies.copy(s.h_in, src + off, len);
+                k_in = s.hd_in;
+            }
+            k_out = direct_out ? reinterpret_cast<void *>(dev_out + off) : s.hd_out;
         }
-        if (hipMemcpyAsync(s.d_in, from, len, hipMemcpyHostToDevice, s.stream) != hipSuccess) {
-            st = AESGPU_EHIP;
-            break;
-        }
-        st = launch_chunk(pl->ctx, key, *op, src, off, s.d_in, s.d_out, len, s.stream);
+        st = launch_chunk(pl->ctx, key, *op, src, off, k_in, k_out, len, s.stream);
         if (st != AESGPU_OK) break;
-        s.staged_out = !pinned_out;
-        void *to = pinned_out ? static_cast<void *>(dst + off) : s.h_out;
-        if (hipMemcpyAsync(to, s.d_out, len, hipMemcpyDeviceToHost, s.stream) != hipSuccess ||
-            hipEventRecord(s.done, s.stream) != hipSuccess) {
+        if (dma) {
+            s.staged_out = !pinned_out;
+            void *to = pinned_out ? static_cast<void *>(dst + off) : s.h_out;
+            if (hipMemcpyAsync(to, s.d_out, len, hipMemcpyDeviceToHost, s.stream) != hipSuccess) {
+                st = AESGPU_EHIP;
+                break;
+            }
+        } else {
+            s.staged_out = !direct_out;
+        }
+        if (hipEventRecord(s.done, s.stream) != hipSuccess) {
             st = AESGPU_EHIP;
             break;
         }
@@ -265,7 +394,7 @@ int aesgpu_pipeline_run(aesgpu_pipeline *pl, const aesgpu_key *key, const aesgpu
     }
     // Drain in issue order (so staged copies land before the call returns).
     for (uint64_t k = 0; k < n_slots; ++k) {
-        const int fs = finish(pl->slots[(c + k) % n_slots], dst);
+        const int fs = finish(pl, pl->slots[(c + k) % n_slots], dst);
         if (st == AESGPU_OK) st = fs;
     }
     if (st != AESGPU_OK) (void)hipGetLastError();

@@ -41,17 +41,20 @@ def expected(op, A, key, data, nonce, ctr0, iv):
 OPS = ["ECB_ENCRYPT", "ECB_DECRYPT", "CTR", "CTR_LE128", "CBC_DECRYPT"]
 
 
-# Host memory kinds: pageable (staged through pinned buffers), pinned with
-# zero copy (the kernel reads and writes host memory), pinned with DMA copies.
-MEMS = ["pageable", "zero_copy", "dma"]
+# Host memory kinds: pageable (staged through pinned buffers that the kernel
+# reads and writes), pageable with DMA copies, pinned with zero copy (the
+# kernel reads and writes the caller's memory), pinned with DMA copies.
+MEMS = ["pageable", "pageable_dma", "zero_copy", "dma"]
+PINNED = ("zero_copy", "dma")
+DMA = ("pageable_dma", "dma")
 
 
 @pytest.mark.parametrize("opname", OPS)
 @pytest.mark.parametrize("mem", MEMS)
 def test_pipeline_matches_oracle(A, ctx, opname, mem):
     op = getattr(A, f"AESGPU_OP_{opname}")
-    pinned = mem != "pageable"
-    flags = A.AESGPU_PIPELINE_COPY if mem == "dma" else 0
+    pinned = mem in PINNED
+    flags = A.AESGPU_PIPELINE_COPY if mem in DMA else 0
     whole = op in (A.AESGPU_OP_ECB_ENCRYPT, A.AESGPU_OP_ECB_DECRYPT, A.AESGPU_OP_CBC_DECRYPT)
     rng = np.random.default_rng(7000 + op + 10 * MEMS.index(mem))
     kb = (16, 24, 32)[op % 3]
@@ -94,14 +97,14 @@ def test_pipeline_matches_oracle(A, ctx, opname, mem):
 
 @pytest.mark.parametrize("mem", MEMS)
 def test_pipeline_in_place(A, ctx, mem):
-    pinned = mem != "pageable"
+    pinned = mem in PINNED
     rng = np.random.default_rng(7100 + MEMS.index(mem))
     key = rng.integers(0, 256, 16, dtype=np.uint8)
     k = A.aesgpu_expand_key(key)
     nonce = rng.integers(0, 256, 12, dtype=np.uint8)
     n = 3 * CHUNK + 16 * 5 + 3
     data = rng.integers(0, 256, n, dtype=np.uint8)
-    pl = A.aesgpu_pipeline_create(ctx, CHUNK, 2, A.AESGPU_PIPELINE_COPY if mem == "dma" else 0)
+    pl = A.aesgpu_pipeline_create(ctx, CHUNK, 2, A.AESGPU_PIPELINE_COPY if mem in DMA else 0)
     addr = None
     try:
         if pinned:
@@ -122,17 +125,55 @@ def test_pipeline_in_place(A, ctx, mem):
         A.aesgpu_pipeline_destroy(pl)
 
 
-@pytest.mark.parametrize("mem", ["zero_copy", "dma"])
+@pytest.mark.parametrize("direction", ["pinned_in", "pinned_out"])
+@pytest.mark.parametrize("copy", [False, True])
+def test_pipeline_mixed_memory(A, ctx, direction, copy):
+    """One side pinned, the other pageable: chunks read or write the pinned
+    side directly (or by DMA) and stage the other; 4 MiB chunks, so every
+    staging copy is split over the copy threads."""
+    rng = np.random.default_rng(7150 + 2 * (direction == "pinned_out") + copy)
+    key = rng.integers(0, 256, 24, dtype=np.uint8)
+    k = A.aesgpu_expand_key(key)
+    iv = rng.integers(0, 256, 16, dtype=np.uint8)
+    n = 3 * (4 << 20) + 16 * 777
+    data = rng.integers(0, 256, n, dtype=np.uint8)
+    log(f"case: pipeline mixed memory {direction} copy={copy} n={n}")
+    addr, pb = A.aesgpu_host_alloc(n)
+    pl = A.aesgpu_pipeline_create(ctx, 4 << 20, 3, A.AESGPU_PIPELINE_COPY if copy else 0)
+    try:
+        want = oracle.cbc_decrypt(key, iv, data)
+        o = A.make_host_op(A.AESGPU_OP_CBC_DECRYPT, iv=iv)
+        if direction == "pinned_in":
+            pb[:] = data
+            out = np.full(n, 0x5A, dtype=np.uint8)
+            A.aesgpu_pipeline_run(pl, k, o, pb, out, n)
+            assert np.array_equal(out, want)
+        else:
+            pb[:] = 0x5A
+            A.aesgpu_pipeline_run(pl, k, o, data, pb, n)
+            assert np.array_equal(np.asarray(pb), want)
+    finally:
+        A.aesgpu_pipeline_destroy(pl)
+        A.aesgpu_host_free(addr)
+
+
+@pytest.mark.parametrize("mem", ["zero_copy", "dma", "pageable"])
 def test_pipeline_large_default_chunks(A, ctx, mem):
-    """64 MiB + a tail, pinned both ways (one zero-copy kernel, or 8 MiB DMA
-    chunks on 3 slots), compared on sampled blocks and by a full round trip."""
+    """64 MiB + a tail: pinned both ways (one zero-copy kernel, or 8 MiB DMA
+    chunks on 3 slots) or pageable (8 MiB staged chunks), compared on sampled
+    blocks and by a full round trip."""
     rng = np.random.default_rng(7200)
     key = rng.integers(0, 256, 32, dtype=np.uint8)
     k = A.aesgpu_expand_key(key)
     nonce = rng.integers(0, 256, 12, dtype=np.uint8)
     n = (64 << 20) + 16 * 1000 + 9
-    a_in, h_in = A.aesgpu_host_alloc(n)
-    a_out, h_out = A.aesgpu_host_alloc(n)
+    log(f"case: pipeline 64 MiB {mem}")
+    if mem == "pageable":
+        a_in, h_in = None, np.empty(n, dtype=np.uint8)
+        a_out, h_out = None, np.empty(n, dtype=np.uint8)
+    else:
+        a_in, h_in = A.aesgpu_host_alloc(n)
+        a_out, h_out = A.aesgpu_host_alloc(n)
     pl = A.aesgpu_pipeline_create(ctx, 0, 0, A.AESGPU_PIPELINE_COPY if mem == "dma" else 0)
     try:
         h_in[:] = rng.integers(0, 256, n, dtype=np.uint8)
@@ -151,8 +192,9 @@ def test_pipeline_large_default_chunks(A, ctx, mem):
         assert np.array_equal(np.asarray(h_out), np.asarray(h_in))
     finally:
         A.aesgpu_pipeline_destroy(pl)
-        A.aesgpu_host_free(a_in)
-        A.aesgpu_host_free(a_out)
+        for a in (a_in, a_out):
+            if a is not None:
+                A.aesgpu_host_free(a)
 
 
 def test_pipeline_errors(A, ctx):
