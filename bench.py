@@ -189,11 +189,13 @@ def batched_bench(torch, A, ctx, rates: dict, reps: int) -> dict:
                         "persistent launch with device key expansion, hipGraph replay"}
 
 
-def serving_bench(torch, A, ctx, n_requests: int) -> dict:
+def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None) -> dict:
     """Poisson arrivals of ECB requests (64 B..16 MiB log-uniform, half encrypt,
     half decrypt, keys from a resident pool of 1,024), replayed natively
     against the continuous-batching server at fractions of its measured
-    saturation rate."""
+    saturation rate.  With the single-buffer rates, the saturation time is
+    also compared with every request at the 1 GiB single-buffer rate of its
+    key size and direction."""
     import numpy as np
 
     from paper_1201_0398_amd import workloads
@@ -228,7 +230,14 @@ def serving_bench(torch, A, ctx, n_requests: int) -> dict:
         log(f"serving at {frac:.2f} of saturation: {points[-1]}")
     st = A.aesgpu_server_get_stats(server)
     A.aesgpu_server_destroy(server)
-    return {"saturation_GB_s": round(total / (n_requests / lam_sat) / 1e9, 1),
+    extra = {}
+    if rates:
+        bits = tr.pool_bits[tr.key_ids]
+        t_ref = sum(float(tr.sizes[(bits == b) & (tr.dirs == d)].sum()) /
+                    rates[(b, "ecb_dec" if d else "ecb_enc")]
+                    for b in (128, 192, 256) for d in (0, 1))
+        extra["saturation_time_vs_single_buffer_mix"] = round((n_requests / lam_sat) / t_ref, 3)
+    return {**extra, "saturation_GB_s": round(total / (n_requests / lam_sat) / 1e9, 1),
             "saturation_req_s": round(lam_sat, 1), "requests_per_point": n_requests,
             "mean_request_bytes": round(total / n_requests, 1), "arena_bytes": arena,
             "batches": int(st.batches), "points": points,
@@ -353,11 +362,31 @@ def cpu_baseline(sample_bytes: int) -> dict:
     ks = oracle.ctr(key, w.nonce, w.ctr0, w.data, threads=threads)
     dt = time.perf_counter() - t0
     assert np.array_equal(pt, w.data) and ks.size == w.data.size
+    # One core, as the paper compares (section 3.1): the literal oracle, and
+    # the oracle's own T-table path (the same algorithm as the GPU's, as the
+    # paper's CPU implementation was), AES-128 ECB encryption.
+    n1, nt = 1 << 20, 16 << 20
+    t1 = time.perf_counter()
+    oracle.ecb_encrypt(key, w.data[:n1], threads=1)
+    t1 = time.perf_counter() - t1
+    tt = time.perf_counter()
+    oracle.ttable_ecb(key, w.data[:nt])
+    tt = time.perf_counter() - tt
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
     return {"value": round(3 * sample_bytes / dt / 1e9, 6), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
             "sample": f"AES-128 ECB encrypt + ECB decrypt + CTR of the first {sample_bytes >> 20} "
                       f"MiB of the 1 GiB seed-1 workload, literal FIPS-197 oracle, "
-                      f"{threads} threads, {dt:.1f} s"}
+                      f"{threads} threads, {dt:.1f} s",
+            "one_core_GB_s": {"literal_ecb_encrypt_1MiB": round(n1 / t1 / 1e9, 6),
+                              "ttable_ecb_encrypt_16MiB": round(nt / tt / 1e9, 6)},
+            "host_cpu": model}
 
 
 def main() -> int:
@@ -472,7 +501,8 @@ def main() -> int:
         del d_pt, d_ctr
         out["batched"] = batched_bench(torch, A, ctx, rates, args.batched_reps)
     if not args.no_serving:
-        out["serving"] = serving_bench(torch, A, ctx, args.serve_requests)
+        out["serving"] = serving_bench(torch, A, ctx, args.serve_requests,
+                                       None if args.no_batched else rates)
     if not args.no_cbc_batch:
         out["batched_cbc"] = cbc_batch_bench(torch, A, ctx, args.batched_reps)
     if not args.no_pipeline:

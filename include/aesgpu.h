@@ -312,8 +312,10 @@ void aesgpu_pipeline_destroy(aesgpu_pipeline *pl);
 /* ------------------------------------------------------------------------ */
 
 /*
- * First-fit allocator of byte ranges [0, capacity) with coalescing on
- * release, in multiples of `granule` (a power of two dividing capacity).  It
+ * Best-fit allocator of byte ranges [0, capacity) with coalescing on
+ * release, in multiples of `granule` (a power of two dividing capacity): an
+ * allocation takes the start of the smallest free range that fits (the
+ * lowest offset among equal sizes), in O(log n) for n free ranges.  It
  * only does the bookkeeping (no device memory is touched); the server admits
  * requests with it.  Not thread-safe.  Errors: EINVAL (bad sizes, a release
  * that is not a live allocation), ENOMEM; aesgpu_arena_alloc returns EAGAIN
@@ -342,8 +344,9 @@ typedef struct {
     uint32_t max_batch_requests; /* 0 = no limit */
     uint64_t max_batch_bytes;    /* 0 = no limit */
     uint32_t max_queued;         /* waiting requests before EAGAIN (0 = 2^20) */
-    uint32_t direct_requests;    /* batches of at most this many requests run as one
-                                    single-buffer launch per request (0 = 4, at most 16;
+    uint32_t direct_requests;    /* batches of at most this many requests, with none
+                                    waiting behind them, run as one single-buffer launch
+                                    per request (0 = 4, at most 16;
                                     AESGPU_SERVER_NO_DIRECT: always the batched kernel) */
 } aesgpu_server_config;
 
@@ -393,8 +396,9 @@ typedef struct {
  * dispatch launches all admitted requests as one batched run (the persistent
  * launch of aesgpu_batch_run, with resident schedules instead of device key
  * expansion, after an upload of the batch's descriptors); a batch of at most
- * direct_requests requests instead runs as one single-buffer kernel per
- * request with the round keys as kernel arguments, which saves the upload.
+ * direct_requests requests, when no other request is waiting, instead runs as
+ * one single-buffer kernel per request with the round keys as kernel
+ * arguments, which saves the upload.
  * Errors: EINVAL, EKEYLEN, ENOMEM, EHIP.
  */
 int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *key_bits,

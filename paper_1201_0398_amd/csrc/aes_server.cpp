@@ -2,7 +2,7 @@
 //
 // Requests (encrypt or decrypt one device buffer in ECB with a key from a
 // resident pool) enter a FIFO.  A dispatcher thread admits requests in order
-// as long as their output fits in a device arena (first-fit ranges), and
+// as long as their output fits in a device arena (best-fit ranges), and
 // whenever one of its streams is idle it launches every admitted request as
 // one batched run (the persistent kernel of the batched path, reading the
 // pool's key schedules that stay resident on the device), or, for a batch of
@@ -22,39 +22,55 @@
 #include <map>
 #include <mutex>
 #include <new>
+#include <set>
 #include <thread>
 #include <vector>
 
 #include "aes_batch.h"
 #include "aes_internal.h"
 
-// ---- first-fit range allocator ---------------------------------------------------
+// ---- best-fit range allocator ----------------------------------------------------
+//
+// Free ranges are indexed twice: by offset (to coalesce on release) and by
+// (size, offset) (to find the smallest range that fits in O(log n)).  A
+// scan over the free list, as first fit does, costs O(free ranges) per
+// allocation; the server admits thousands of requests in one batch under its
+// lock, and a fragmented list then stalls the dispatcher.
 
 struct aesgpu_arena {
     uint64_t capacity = 0;
     uint64_t granule = 256;
     uint64_t used = 0;
     uint64_t high_water = 0;
-    std::map<uint64_t, uint64_t> free_ranges;  // offset -> length, non-adjacent
-    std::map<uint64_t, uint64_t> live;         // offset -> length of each allocation
+    std::map<uint64_t, uint64_t> free_ranges;           // offset -> length, non-adjacent
+    std::set<std::pair<uint64_t, uint64_t>> by_size;    // (length, offset) of each free range
+    std::map<uint64_t, uint64_t> live;                  // offset -> length of each allocation
 
     uint64_t round(uint64_t n) const { return (n + granule - 1) / granule * granule; }
 
+    void add_free(uint64_t off, uint64_t len) {
+        free_ranges.emplace(off, len);
+        by_size.emplace(len, off);
+    }
+    void remove_free(std::map<uint64_t, uint64_t>::iterator it) {
+        by_size.erase({it->second, it->first});
+        free_ranges.erase(it);
+    }
+
+    // The smallest free range that fits (the lowest offset among equal
+    // lengths); the allocation takes its start.
     bool alloc(uint64_t n, uint64_t *off) {
         const uint64_t need = round(n ? n : 1);
-        for (auto it = free_ranges.begin(); it != free_ranges.end(); ++it) {
-            if (it->second < need) continue;
-            *off = it->first;
-            const uint64_t rest = it->second - need;
-            const uint64_t at = it->first + need;
-            free_ranges.erase(it);
-            if (rest) free_ranges.emplace(at, rest);
-            live.emplace(*off, need);
-            used += need;
-            high_water = std::max(high_water, used);
-            return true;
-        }
-        return false;
+        auto fit = by_size.lower_bound({need, 0});
+        if (fit == by_size.end()) return false;
+        const uint64_t len = fit->first, at = fit->second;
+        remove_free(free_ranges.find(at));
+        if (len > need) add_free(at + need, len - need);
+        live.emplace(at, need);
+        used += need;
+        high_water = std::max(high_water, used);
+        *off = at;
+        return true;
     }
 
     // Returns false unless [off, off + n) is exactly a live allocation.
@@ -63,30 +79,28 @@ struct aesgpu_arena {
         auto a = live.find(off);
         if (a == live.end() || a->second != len) return false;
         live.erase(a);
-        auto next = free_ranges.lower_bound(off);
         uint64_t start = off, size = len;
+        auto next = free_ranges.lower_bound(off);
         if (next != free_ranges.end() && next->first == off + len) {
             size += next->second;
-            next = free_ranges.erase(next);
+            auto after = std::next(next);
+            remove_free(next);
+            next = after;
         }
         if (next != free_ranges.begin()) {
             auto prev = std::prev(next);
             if (prev->first + prev->second == off) {
                 start = prev->first;
                 size += prev->second;
-                free_ranges.erase(prev);
+                remove_free(prev);
             }
         }
-        free_ranges.emplace(start, size);
+        add_free(start, size);
         used -= len;
         return true;
     }
 
-    uint64_t largest_free() const {
-        uint64_t m = 0;
-        for (const auto &r : free_ranges) m = std::max(m, r.second);
-        return m;
-    }
+    uint64_t largest_free() const { return by_size.empty() ? 0 : by_size.rbegin()->first; }
 };
 
 extern "C" {
@@ -100,7 +114,7 @@ int aesgpu_arena_create(uint64_t capacity, uint64_t granule, aesgpu_arena **out)
     if (!a) return AESGPU_ENOMEM;
     a->capacity = capacity;
     a->granule = granule;
-    a->free_ranges.emplace(0, capacity);
+    a->add_free(0, capacity);
     *out = a;
     return AESGPU_OK;
 }
@@ -203,13 +217,18 @@ bool ensure(void **p, size_t *cap, size_t need, bool pinned) {
     return true;
 }
 
-// Launches the requests in slot.reqs; returns an AESGPU status.
-int launch_slot(aesgpu_server *s, Slot &slot) {
+// Launches the requests in slot.reqs; returns an AESGPU status.  `backlog`:
+// requests were still waiting after this batch was admitted.
+int launch_slot(aesgpu_server *s, Slot &slot, bool backlog) {
     const size_t m = slot.reqs.size();
-    if (s->cfg.direct_requests != AESGPU_SERVER_NO_DIRECT && m <= s->cfg.direct_requests) {
-        // A few requests: the single-buffer kernel, round keys as kernel
-        // arguments.  Nothing is copied to the device first, so a small batch
-        // costs its launches only, and each request gets the whole chip.
+    if (!backlog && s->cfg.direct_requests != AESGPU_SERVER_NO_DIRECT &&
+        m <= s->cfg.direct_requests) {
+        // A few requests and none queued behind them: the single-buffer
+        // kernel, round keys as kernel arguments.  Nothing is copied to the
+        // device first, so a small batch costs its launches only, and each
+        // request gets the whole chip.  Under a backlog the dispatcher thread
+        // itself is the limit, and one batched launch per batch costs it less
+        // than one launch per request.
         for (const Req &r : slot.reqs) {
             const bool dec = r.dir == AESGPU_DIR_DECRYPT;
             LaunchArgs a{};
@@ -343,6 +362,7 @@ void worker_main(aesgpu_server *s) {
         // 2. Admission and launch on every idle stream.
         for (Slot &slot : s->slots) {
             if (slot.busy) continue;
+            bool backlog = false;
             {
                 std::lock_guard<std::mutex> g(s->mu);
                 uint64_t bytes = 0;
@@ -360,11 +380,12 @@ void worker_main(aesgpu_server *s) {
                     slot.reqs.push_back(r);
                     s->waiting.pop_front();
                 }
+                backlog = !s->waiting.empty();
             }
             if (slot.reqs.empty()) break;
             const double t = s->now();
             for (Req &r : slot.reqs) r.t_launch = t;
-            const int st = launch_slot(s, slot);
+            const int st = launch_slot(s, slot, backlog);
             std::lock_guard<std::mutex> g(s->mu);
             s->stats.batches++;
             s->stats.max_batch_requests =
@@ -444,7 +465,7 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
     s->h_sched = sched;
     s->arena.capacity = c.arena_bytes;
     s->arena.granule = 256;
-    s->arena.free_ranges.emplace(0, c.arena_bytes);
+    s->arena.add_free(0, c.arena_bytes);
     s->slots.resize(c.n_streams);
     s->t0 = Clock::now();
     {

@@ -1,6 +1,9 @@
-"""The server's first-fit range allocator (host logic, no GPU): every offset
-matches a plain first-fit model with coalescing, live ranges never overlap,
-and releases of anything but a live range are rejected."""
+"""The server's best-fit range allocator (host logic, no GPU): every offset
+matches a plain best-fit model with coalescing, live ranges never overlap,
+releases of anything but a live range are rejected, and allocation stays
+fast when the free list is fragmented."""
+import time
+
 import numpy as np
 import pytest
 
@@ -11,8 +14,10 @@ def A():
     return aesgpu
 
 
-class FirstFit:
-    """Reference model: a sorted list of free [start, end) ranges."""
+class BestFit:
+    """Reference model: a sorted list of free [start, end) ranges; an
+    allocation takes the start of the smallest range that fits, the lowest
+    offset among equal sizes."""
 
     def __init__(self, cap, granule):
         self.g = granule
@@ -24,11 +29,13 @@ class FirstFit:
 
     def alloc(self, n):
         need = self.rnd(n)
-        for i, (a, b) in enumerate(self.free):
-            if b - a >= need:
-                self.free[i:i + 1] = [(a + need, b)] if b - a > need else []
-                return a
-        return None
+        fits = [(b - a, a, i) for i, (a, b) in enumerate(self.free) if b - a >= need]
+        if not fits:
+            return None
+        _, a, i = min(fits)
+        b = self.free[i][1]
+        self.free[i:i + 1] = [(a + need, b)] if b - a > need else []
+        return a
 
     def release(self, off, n):
         self.free.append((off, off + self.rnd(n)))
@@ -43,11 +50,11 @@ class FirstFit:
 
 
 @pytest.mark.parametrize("seed", range(5))
-def test_matches_first_fit_model(A, seed):
+def test_matches_best_fit_model(A, seed):
     rng = np.random.default_rng(seed)
     cap, g = 1 << 20, 256
     arena = A.aesgpu_arena_create(cap, g)
-    model = FirstFit(cap, g)
+    model = BestFit(cap, g)
     live = {}
     try:
         for step in range(3000):
@@ -93,3 +100,42 @@ def test_errors_and_coalescing(A):
     for cap, g in ((1000, 256), (4096, 100), (0, 256)):
         with pytest.raises(A.AesgpuError):
             A.aesgpu_arena_create(cap, g)
+
+
+def test_best_fit_choice(A):
+    """A small request goes to the smallest free range that fits, not the
+    first one: first fit would split the 1 KiB hole at offset 0."""
+    arena = A.aesgpu_arena_create(4096, 256)
+    try:
+        a, b, c, d = (A.aesgpu_arena_alloc(arena, n) for n in (1024, 1024, 256, 1792))
+        assert (a, b, c, d) == (0, 1024, 2048, 2304)
+        A.aesgpu_arena_release(arena, a, 1024)
+        A.aesgpu_arena_release(arena, c, 256)
+        assert A.aesgpu_arena_alloc(arena, 200) == 2048      # the 256-byte hole
+        assert A.aesgpu_arena_alloc(arena, 256) == 0         # then the 1 KiB one
+        assert A.aesgpu_arena_query(arena)[1] == 768
+    finally:
+        A.aesgpu_arena_destroy(arena)
+
+
+def test_fragmented_free_list_stays_fast(A):
+    """100,000 free 256-byte holes, then 20,000 requests that fit none of
+    them: each allocation is a search in a size index, not a scan of the
+    holes (a scan would take about 2e9 steps here)."""
+    g = 256
+    n_holes = 100_000
+    arena = A.aesgpu_arena_create(1 << 30, g)
+    try:
+        offs = [A.aesgpu_arena_alloc(arena, g) for _ in range(2 * n_holes)]
+        for off in offs[::2]:
+            A.aesgpu_arena_release(arena, off, g)
+        t0 = time.perf_counter()
+        got = [A.aesgpu_arena_alloc(arena, 2 * g) for _ in range(20_000)]
+        dt = time.perf_counter() - t0
+        assert got[0] == 2 * n_holes * g and got == sorted(got)
+        assert dt < 3.0, f"20,000 allocations took {dt:.2f} s"
+        used, largest, _ = A.aesgpu_arena_query(arena)
+        assert used == n_holes * g + 20_000 * 2 * g
+        assert largest == (1 << 30) - 2 * n_holes * g - 20_000 * 2 * g
+    finally:
+        A.aesgpu_arena_destroy(arena)
