@@ -88,6 +88,63 @@ def test_mixed_batch_matches_oracle(A, ctx, bpl, tile):
         A.aesgpu_batch_free(plan)
 
 
+@pytest.mark.parametrize("bpl,tile", [(1, 64), (2, 128), (4, 256), (4, 512), (2, 8192)])
+def test_ctr_counter_alignment_in_batches(A, ctx, bpl, tile):
+    """CTR messages whose first counter sits at every kind of offset from the
+    kernel's step (64 * blocks per lane): 0, 1, one short of a step, a step,
+    255, 256, random, and the largest counter that still fits 32 bits; lengths
+    from one partial block to several tiles, with and without a partial last
+    block.  Every byte must match the oracle and nothing outside the
+    messages may change."""
+    import torch
+    rng = np.random.default_rng(77 + bpl + tile)
+    step = 64 * bpl
+    starts = [0, 1, step - 1, step, step + 1, 255, 256, 257, 3 * step - 5]
+    lens = [5, 16, 16 * step - 16, 16 * step, 16 * step + 9, 16 * (tile + step) + 3,
+            16 * 3 * tile + 7, 16 * 2 * tile]
+    ctr0s, lengths = [], []
+    for c in starts:
+        for L in lens:
+            ctr0s.append(c + int(rng.integers(0, 1 << 20)) * 256)
+            lengths.append(L)
+    # Largest first counters: the message's last block uses counter 2^32 - 1.
+    for L in (16 * step + 9, 16 * (tile + 1), 16):
+        lengths.append(L)
+        ctr0s.append((1 << 32) - (L + 15) // 16)
+    m = len(lengths)
+    lengths = np.array(lengths)
+    span = 16 * ((lengths + 15) // 16) + 16
+    in_off = np.concatenate([[0], np.cumsum(span)[:-1]])
+    out_off = in_off.copy()
+    bits = np.array([128, 192, 256])[rng.integers(0, 3, size=m)]
+    keys = np.zeros((m, 32), dtype=np.uint8)
+    for j in range(m):
+        keys[j, : bits[j] // 8] = rng.integers(0, 256, bits[j] // 8, dtype=np.uint8)
+    nonces = rng.integers(0, 256, (m, 12), dtype=np.uint8)
+    ctr0 = np.array(ctr0s, dtype=np.uint64)
+    total = int(span.sum())
+    data = rng.integers(0, 256, total, dtype=np.uint8)
+    log(f"case: {m} CTR messages, bpl={bpl} tile={tile}, {total} bytes")
+    msgs = A.make_msgs(in_off, out_off, lengths, np.arange(m), bits, np.ones(m, dtype=np.int64),
+                       np.zeros(m, dtype=np.int64), nonces, ctr0)
+    plan = A.aesgpu_batch_plan(ctx, msgs, blocks_per_lane=bpl, tile_blocks=tile)
+    try:
+        d_out = torch.full((total,), 0x5A, dtype=torch.uint8, device="cuda")
+        A.aesgpu_batch_run(plan, to_dev(keys.reshape(-1)), m, to_dev(data), d_out)
+        out = from_dev(d_out)
+        covered = np.zeros(total, dtype=bool)
+        for j in range(m):
+            o, L = int(out_off[j]), int(lengths[j])
+            key = keys[j, : bits[j] // 8]
+            want = oracle.ctr(key, nonces[j], int(ctr0[j]), data[o:o + L])
+            assert np.array_equal(out[o:o + L], want), \
+                f"message {j}: ctr0 {int(ctr0[j])} (mod step {int(ctr0[j]) % step}) len {L}"
+            covered[o:o + L] = True
+        assert (out[~covered] == 0x5A).all(), "wrote outside the messages"
+    finally:
+        A.aesgpu_batch_free(plan)
+
+
 def test_graph_replays_match_direct_launch(A, ctx):
     import torch
     rng = np.random.default_rng(41)
