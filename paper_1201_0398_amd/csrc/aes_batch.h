@@ -42,9 +42,12 @@ constexpr uint32_t kCbcGroupMsgs = 16;
 // followed by 64 equivalent-inverse-cipher words.
 constexpr uint32_t kSchedWords = 128;
 
-// Device bytes after the tiles: 2 queue counters (zero before each run) and
-// one scratch flag per workgroup (at most 1024 workgroups).
+// Device bytes of a launch's counters: 2 queue counters, one scratch flag per
+// workgroup (at most 1024 workgroups), then the count of workgroups that have
+// finished.  The counters must be zero before the first launch; the last
+// workgroup of every launch zeroes the queue counters and the count again.
 constexpr size_t kCounterBytes = 4 * (2 + 1024) + 56;
+constexpr uint32_t kExitWord = 2 + 1024;
 
 struct BatchTotals {
     uint64_t total = 0;    // sum of message bytes
@@ -62,7 +65,7 @@ struct BatchLaunch {
     const DevMsg *msgs;
     const Tile *tiles[2];
     uint32_t n_tiles[2];
-    uint32_t *counters;      // kCounterBytes: two tile counters, then per-workgroup flags
+    uint32_t *counters;      // kCounterBytes, zero before the launch (see kCounterBytes)
     const uint8_t *keys;     // raw keys (expanded on the device), or
     const uint32_t *sched;   // resident schedules (kSchedWords per slot)
     const uint8_t *in;
@@ -75,7 +78,6 @@ struct BatchLaunch {
     int n_cu;
     uint32_t bpl;
     uint64_t blocks[2];      // blocks per set, to split the workgroups
-    bool reset_counters;     // launch a counter reset first (else already zero)
 };
 
 // Validates messages and cuts them into tiles of at most tile_blocks blocks,
@@ -85,8 +87,8 @@ int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vec
                 std::vector<Tile> (&tiles)[2], std::vector<uint32_t> &cbc_list,
                 std::vector<Tile> &cbc_groups, BatchTotals &tot);
 
-// Optional counter reset, then one persistent launch over both queues, then
-// (if the batch has CBC-encrypt messages) the CBC-encryption launch.
+// One persistent launch over both queues, then (if the batch has CBC-encrypt
+// messages) the CBC-encryption launch.
 int enqueue_batch(const BatchLaunch &L, hipStream_t stream);
 
 }  // namespace aesgpu

@@ -580,18 +580,27 @@ __global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
             drain_queue<true, BPL>(lds, b, p, start);
         }
     }
-}
-
-__global__ void reset_counters(uint32_t *c, uint32_t n) {
-    if (threadIdx.x < n) c[threadIdx.x] = 0;
+    // The last workgroup to finish zeroes the two queue counters (and the
+    // exit count), so the next launch on these counters needs no reset
+    // kernel before it: every workgroup counts itself out after its last
+    // pull, so no pull of this launch can follow the reset.
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        uint32_t *exits = p.counters + kExitWord;
+        const uint32_t before = __hip_atomic_fetch_add(exits, 1u, __ATOMIC_ACQ_REL,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+        if (before == gridDim.x - 1) {
+            __hip_atomic_store(&p.counters[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(&p.counters[1], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __hip_atomic_store(exits, 0u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 template <int BPL>
 int enqueue_t(const BatchLaunch &L, hipStream_t s) {
     const uint32_t total = L.n_tiles[0] + L.n_tiles[1];
     if (!total && !L.n_cbc_groups) return AESGPU_OK;
-    if (L.reset_counters && total)
-        hipLaunchKernelGGL(reset_counters, dim3(1), dim3(64), 0, s, L.counters, 2u);
     // About one tile per wave for small batches, one workgroup per CU at most.
     constexpr uint32_t kWaves = kWG / 64;
     uint32_t grid = (total + kWaves - 1) / kWaves;
@@ -772,7 +781,6 @@ int enqueue(aesgpu_batch *b, const uint8_t *keys, const void *in, void *out, hip
     L.bpl = b->bpl;
     L.blocks[0] = b->tot.blocks[0];
     L.blocks[1] = b->tot.blocks[1];
-    L.reset_counters = true;
     return enqueue_batch(L, s);
 }
 
@@ -853,6 +861,10 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     if (msg_bytes) ok &= hipMemcpy(b->d_msgs, dm.data(), msg_bytes, hipMemcpyHostToDevice) == hipSuccess;
     if (t0) ok &= hipMemcpy(b->d_tiles[0], tiles[0].data(), t0, hipMemcpyHostToDevice) == hipSuccess;
     if (t1) ok &= hipMemcpy(b->d_tiles[1], tiles[1].data(), t1, hipMemcpyHostToDevice) == hipSuccess;
+    // The queue counters start at zero once; every launch leaves them zero.
+    const std::vector<uint8_t> zeros(kCounterBytes, 0);
+    ok &= hipMemcpy(b->d_counters, zeros.data(), kCounterBytes, hipMemcpyHostToDevice) ==
+          hipSuccess;
     ok &= hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) == hipSuccess;
     if (!ok) {
         aesgpu_batch_free(b);

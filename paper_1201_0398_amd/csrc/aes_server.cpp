@@ -169,6 +169,7 @@ struct Slot {
     size_t d_cap = 0;
     void *h_buf = nullptr;   // pinned staging of the same layout
     size_t h_cap = 0;
+    uint32_t *d_counters = nullptr;  // the batch kernel's counters (kCounterBytes, kept zero)
     bool busy = false;
     std::vector<Req> reqs;
 };
@@ -281,7 +282,7 @@ int launch_slot(aesgpu_server *s, Slot &slot, bool backlog) {
     if (st != AESGPU_OK) return st;
     const size_t mb = m * sizeof(DevMsg), t0 = tiles[0].size() * sizeof(Tile),
                  t1 = tiles[1].size() * sizeof(Tile);
-    const size_t bytes = mb + t0 + t1 + kCounterBytes;
+    const size_t bytes = mb + t0 + t1;
     if (!ensure(&slot.h_buf, &slot.h_cap, bytes, true) ||
         !ensure(&slot.d_buf, &slot.d_cap, bytes, false))
         return AESGPU_ENOMEM;
@@ -289,19 +290,17 @@ int launch_slot(aesgpu_server *s, Slot &slot, bool backlog) {
     std::memcpy(h, dm.data(), mb);
     std::memcpy(h + mb, tiles[0].data(), t0);
     std::memcpy(h + mb + t0, tiles[1].data(), t1);
-    std::memset(h + mb + t0 + t1, 0, 8);  // the two tile counters start at zero
-    if (hipMemcpyAsync(slot.d_buf, slot.h_buf, mb + t0 + t1 + 8, hipMemcpyHostToDevice,
-                       slot.stream) !=
+    if (hipMemcpyAsync(slot.d_buf, slot.h_buf, bytes, hipMemcpyHostToDevice, slot.stream) !=
         hipSuccess)
         return AESGPU_EHIP;
-    char *d = static_cast<char *>(slot.d_buf);
+    const char *desc = static_cast<const char *>(slot.d_buf);
     BatchLaunch L{};
-    L.msgs = reinterpret_cast<const DevMsg *>(d);
-    L.tiles[0] = reinterpret_cast<const Tile *>(d + mb);
-    L.tiles[1] = reinterpret_cast<const Tile *>(d + mb + t0);
+    L.msgs = reinterpret_cast<const DevMsg *>(desc);
+    L.tiles[0] = reinterpret_cast<const Tile *>(desc + mb);
+    L.tiles[1] = reinterpret_cast<const Tile *>(desc + mb + t0);
     L.n_tiles[0] = uint32_t(tiles[0].size());
     L.n_tiles[1] = uint32_t(tiles[1].size());
-    L.counters = reinterpret_cast<uint32_t *>(d + mb + t0 + t1);
+    L.counters = slot.d_counters;
     L.keys = nullptr;
     L.sched = s->d_sched;
     L.in = nullptr;
@@ -315,7 +314,6 @@ int launch_slot(aesgpu_server *s, Slot &slot, bool backlog) {
     L.bpl = s->cfg.blocks_per_lane;
     L.blocks[0] = tot.blocks[0];
     L.blocks[1] = tot.blocks[1];
-    L.reset_counters = false;  // zeroed by the copy above
     st = enqueue_batch(L, slot.stream);
     if (st != AESGPU_OK) return st;
     return hipEventRecord(slot.done, slot.stream) == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
@@ -421,6 +419,7 @@ void destroy_server(aesgpu_server *s) {
         if (slot.done) (void)hipEventDestroy(slot.done);
         if (slot.stream) (void)hipStreamDestroy(slot.stream);
         if (slot.d_buf) (void)hipFree(slot.d_buf);
+        if (slot.d_counters) (void)hipFree(slot.d_counters);
         if (slot.h_buf) (void)hipHostFree(slot.h_buf);
     }
     if (s->d_sched) (void)hipFree(s->d_sched);
@@ -475,9 +474,13 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
         ok = ok && hipMemcpy(s->d_sched, sched.data(), sched.size() * 4, hipMemcpyHostToDevice) ==
                        hipSuccess;
         ok = ok && hipMalloc(&s->d_arena, c.arena_bytes) == hipSuccess;
+        const std::vector<uint8_t> zeros(kCounterBytes, 0);
         for (Slot &slot : s->slots) {
             ok = ok && hipStreamCreateWithFlags(&slot.stream, hipStreamNonBlocking) == hipSuccess;
             ok = ok && hipEventCreateWithFlags(&slot.done, hipEventDisableTiming) == hipSuccess;
+            ok = ok && hipMalloc(&slot.d_counters, kCounterBytes) == hipSuccess;
+            ok = ok && hipMemcpy(slot.d_counters, zeros.data(), kCounterBytes,
+                                 hipMemcpyHostToDevice) == hipSuccess;
         }
         if (!ok) {
             destroy_server(s);
