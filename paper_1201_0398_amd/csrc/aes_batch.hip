@@ -482,8 +482,8 @@ __device__ void cbc_encrypt_group(const uint32_t *lds, const Bases &b, const Bat
     if (n) out[4 * last + q] = c;
 }
 
-// The CBC-encryption launch: forward tables in LDS, then wave w of the grid
-// takes groups w, w + (waves in the grid), ... (longest first).  Every wave
+// The CBC-encryption launch: forward tables in LDS, then each wave takes
+// every (waves in the grid)-th group from its start (below).  Every wave
 // reaches the end of the list.  WG threads per workgroup, one workgroup per
 // CU: few waves per CU when there are few groups (each lane's chain of
 // blocks is latency-bound), 16 when there are many.
@@ -493,9 +493,12 @@ __global__ __launch_bounds__(WG) void cbc_encrypt_kernel(BatchParams p, const Ti
     __shared__ uint32_t lds[kFwdWords];
     stage_tables<false, WG>(lds, p.tables);
     const Bases b = lane_bases();
+    // Groups are sorted longest first.  Wave w of workgroup b starts on group
+    // w * gridDim.x + b, so the longest groups land on different CUs, each
+    // beside shorter ones that finish early: a group's time is its sequential
+    // chain, and a chain waits less for the LDS on a CU with fewer waves.
     const uint32_t waves = gridDim.x * (blockDim.x / 64u);
-    for (uint32_t g = blockIdx.x * (blockDim.x / 64u) + (threadIdx.x >> 6); g < n_groups;
-         g += waves) {
+    for (uint32_t g = (threadIdx.x >> 6) * gridDim.x + blockIdx.x; g < n_groups; g += waves) {
         const Tile t = load_uniform(groups + __builtin_amdgcn_readfirstlane(g));
         // The first message is the group's longest; all share one key size.
         const DevMsg m0 = load_uniform(p.msgs + as_const(p.cbc_list)[t.msg]);
