@@ -44,6 +44,7 @@ struct BatchParams {
     uint32_t *counters;     // dynamic pulls of each queue, then one flag word per workgroup
     uint32_t n_wg_forward_first;  // workgroups that start on the forward queue
     uint32_t n_static[2];   // tiles handed out statically (one per wave of the starting WGs)
+    uint32_t pull[2];       // consecutive tiles a wave takes per pull of a queue
     const uint8_t *keys;    // raw key bytes, 32-byte stride (device expansion)
     const uint32_t *sched;  // or resident schedules, kSchedWords per key slot
     const uint8_t *in;
@@ -524,13 +525,19 @@ __device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
     const DevMsg *__restrict__ msgs = p.msgs;
     const Tile *__restrict__ tiles = p.tiles[set];
     uint32_t t = first;
+    uint32_t run_end = 0;  // end of the run of tiles taken by the last pull
     for (;;) {
         t = __builtin_amdgcn_readfirstlane(t);
         if (t == kNone) {
             if (p.n_static[set] >= p.n_tiles[set]) break;  // no dynamic tiles at all
+            // One atomic per run of `pull` consecutive tiles (similar in size,
+            // the queue being sorted): all waves of the chip pull from one
+            // counter, whose atomics would otherwise bound batches of many
+            // short tiles.
             uint32_t c = 0;
-            if ((threadIdx.x & 63u) == 0) c = atomicAdd(&p.counters[set], 1u);
+            if ((threadIdx.x & 63u) == 0) c = atomicAdd(&p.counters[set], p.pull[set]);
             t = p.n_static[set] + __builtin_amdgcn_readfirstlane(c);
+            run_end = t + p.pull[set];
         }
         if (t >= p.n_tiles[set]) break;
         // Scalar loads (the index is wave-uniform and nothing writes the
@@ -538,7 +545,7 @@ __device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
         const Tile tile = load_uniform(tiles + t);
         const DevMsg m = load_uniform(msgs + tile.msg);
         run_tile<kInv, BPL>(lds, b, p, m, tile);
-        t = kNone;
+        t = t + 1 < run_end ? t + 1 : kNone;
     }
 }
 
@@ -619,8 +626,16 @@ int enqueue_t(const BatchLaunch &L, hipStream_t s) {
         fwd = uint32_t(share * grid + 0.5);
         fwd = fwd < 1 ? 1 : (fwd > grid - 1 ? grid - 1 : fwd);
     }
+    // Dynamic tiles per pull: about four pulls per wave of the grid for each
+    // queue, at most 32 tiles.
+    uint32_t pull[2] = {1u, 1u};
+    const uint32_t n_static[2] = {fwd * kWaves, (grid - fwd) * kWaves};
+    for (int q = 0; q < 2 && grid; ++q) {  // grid is 0 when only CBC encryption runs
+        const uint32_t dyn = L.n_tiles[q] > n_static[q] ? L.n_tiles[q] - n_static[q] : 0u;
+        pull[q] = std::min<uint32_t>(32u, std::max<uint32_t>(1u, dyn / (grid * kWaves * 4u)));
+    }
     BatchParams p{L.msgs,     {L.tiles[0], L.tiles[1]}, {L.n_tiles[0], L.n_tiles[1]},
-                  L.counters, fwd,  {fwd * kWaves, (grid - fwd) * kWaves},
+                  L.counters, fwd,  {n_static[0], n_static[1]}, {pull[0], pull[1]},
                   L.keys,     L.sched, L.in, L.out, L.tables, L.cbc_list, L.cbc_dummy};
     if (L.n_tiles[0] + L.n_tiles[1])
         hipLaunchKernelGGL((batch_kernel<BPL>), dim3(grid), dim3(kWG), 0, s, p);
