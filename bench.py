@@ -529,6 +529,16 @@ def main() -> int:
                          "reads_per_block": LDS_READS_PER_BLOCK[dominant]},
         "kernels": per_kernel,
     }
+    # The achievable HBM ceiling on this machine: a plain device copy of the same
+    # size (torch's copy kernel), read + write bytes over its event time.
+    copy = lambda: d_pt.copy_(d_in)  # noqa: E731
+    warm_up(torch, copy, 0.1)
+    t_copy = time_call(torch, copy, 20)
+    copy_gbs = 2 * n_bytes / t_copy / 1e9
+    out["copy_ceiling"] = {"copy_GB_s": round(copy_gbs, 1), "unit": "GB/s (read + write)",
+                           "dominant_kernel_frac_of_copy": round(achieved / copy_gbs, 4),
+                           "copy_frac_of_peak": round(copy_gbs / HBM_PEAK_GBS, 4),
+                           "what": f"device-to-device copy of {n_bytes >> 20} MiB"}
     if not args.no_batched:
         rates = single_rates(torch, A, ctx, w, d_in, d_ct)
         out["single_buffer_GB_s"] = {f"aes{b}_{m}": round(v / 1e9, 1) for (b, m), v in rates.items()}
