@@ -260,14 +260,18 @@ int launch_slot(aesgpu_server *s, Slot &slot, bool backlog) {
     }
     uint32_t tile_blocks = s->cfg.tile_blocks;
     if (!tile_blocks) {
-        // Adaptive: about two tiles per wave slot of this stream's share of
-        // the CUs, so that a small batch is still spread over many waves (a
+        // Adaptive: about two tiles per wave slot of this batch's share of
+        // the CUs (the chip divided among it and the batches already in
+        // flight), so that a small batch is still spread over many waves (a
         // lone wave on a long tile is latency bound) while batches of the
         // other streams keep CUs to run on; between one step and 8192 blocks.
+        // The dispatcher thread alone sets and clears the busy flags.
         uint64_t blocks = 0;
         for (const Req &r : slot.reqs) blocks += r.n / 16;
         const uint64_t step = 64ull * s->cfg.blocks_per_lane;
-        const uint64_t share = std::max<uint64_t>(1, uint64_t(s->ctx->n_cu) / s->cfg.n_streams);
+        uint64_t running = 0;
+        for (const Slot &o : s->slots) running += o.busy ? 1 : 0;
+        const uint64_t share = std::max<uint64_t>(1, uint64_t(s->ctx->n_cu) / (1 + running));
         const uint64_t target = 2ull * share * 16;
         uint64_t tb = (blocks + target - 1) / target;
         tb = (tb + step - 1) / step * step;
