@@ -428,7 +428,7 @@ def main() -> int:
     args = parse()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the AES path "
-              f"shards without communication, and this build measures one GPU's share.",
+              f"shards without communication, and this benchmark measures one GPU's share.",
               file=sys.stderr)
         return 2
     import numpy as np

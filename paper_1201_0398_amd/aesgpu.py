@@ -116,8 +116,8 @@ assert ctypes.sizeof(aesgpu_done) == 56 and ctypes.sizeof(aesgpu_request) == 40
 def _load() -> ctypes.CDLL:
     if not os.path.exists(LIB_PATH):
         raise ImportError(
-            f"{LIB_PATH} is missing: build it with `python -c 'import __graft_entry__ as g; "
-            f"g.build()'` (hipcc, gfx950).  There is no fallback path.")
+            f"{LIB_PATH} is missing: build it with `python paper_1201_0398_amd/build.py` "
+            f"(hipcc, gfx950).  There is no fallback path.")
     L = ctypes.CDLL(LIB_PATH)
     vp, sz, ci = ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int
     u8p = ctypes.POINTER(ctypes.c_uint8)
