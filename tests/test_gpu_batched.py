@@ -145,6 +145,61 @@ def test_ctr_counter_alignment_in_batches(A, ctx, bpl, tile):
         A.aesgpu_batch_free(plan)
 
 
+@pytest.mark.parametrize("direction", ["forward", "inverse"])
+def test_many_short_messages_pull_runs(A, ctx, direction):
+    """65,536 one-tile messages (1..4 blocks each, own key each): far more
+    tiles than waves, so waves pull runs of several tiles per atomic (the run
+    length is computed below as the launch computes it).  Forward: ECB
+    encryption and CTR (with partial last blocks); inverse: ECB and CBC
+    decryption.  Every message against the oracle."""
+    import torch
+    rng = np.random.default_rng(4242 + (direction == "inverse"))
+    m = 65536
+    n_cu = A.aesgpu_ctx_num_cus(ctx)
+    grid = min((m + 15) // 16, n_cu, 1024)
+    run = min(32, max(1, (m - 16 * grid) // (16 * grid * 4)))
+    log(f"case: {m} short messages, {direction} queue, {run} tiles per pull")
+    assert run > 1, "the case must exercise multi-tile pulls"
+    blocks = rng.integers(1, 5, size=m)
+    if direction == "forward":
+        modes = rng.integers(0, 2, size=m)                   # ECB or CTR
+        dirs = np.zeros(m, dtype=np.int64)
+        lengths = np.where(modes == 1, 16 * blocks - rng.integers(0, 16, size=m), 16 * blocks)
+    else:
+        modes = np.where(rng.integers(0, 2, size=m) == 1, 2, 0)  # ECB or CBC
+        dirs = np.ones(m, dtype=np.int64)
+        lengths = 16 * blocks
+    bits = np.array([128, 192, 256])[rng.integers(0, 3, size=m)]
+    span = 16 * blocks
+    offs = np.concatenate([[0], np.cumsum(span)[:-1]])
+    keys = rng.integers(0, 256, (m, 32), dtype=np.uint8)
+    nonces = rng.integers(0, 256, (m, 12), dtype=np.uint8)
+    ctr0 = rng.integers(0, 1 << 31, size=m).astype(np.uint32)
+    ivs = rng.integers(0, 256, (m, 16), dtype=np.uint8)
+    total = int(span.sum())
+    data = rng.integers(0, 256, total, dtype=np.uint8)
+    msgs = A.make_msgs(offs, offs, lengths, np.arange(m), bits, modes, dirs, nonces, ctr0, iv=ivs)
+    plan = A.aesgpu_batch_plan(ctx, msgs, blocks_per_lane=4, tile_blocks=8192)
+    try:
+        d_out = torch.zeros(total, dtype=torch.uint8, device="cuda")
+        A.aesgpu_batch_run(plan, to_dev(keys.reshape(-1)), m, to_dev(data), d_out)
+        out = from_dev(d_out)
+    finally:
+        A.aesgpu_batch_free(plan)
+    for j in range(m):
+        o, L = int(offs[j]), int(lengths[j])
+        key = keys[j, : bits[j] // 8]
+        src = data[o:o + L]
+        if modes[j] == 1:
+            want = oracle.ctr(key, nonces[j], int(ctr0[j]), src, threads=1)
+        elif modes[j] == 2:
+            want = oracle.cbc_decrypt(key, ivs[j], src, threads=1)
+        else:
+            want = oracle.ecb(key, src, decrypt=bool(dirs[j]), threads=1)
+        assert np.array_equal(out[o:o + L], want), \
+            f"message {j}: mode {modes[j]} bits {bits[j]} len {L}"
+
+
 def test_graph_replays_match_direct_launch(A, ctx):
     import torch
     rng = np.random.default_rng(41)
