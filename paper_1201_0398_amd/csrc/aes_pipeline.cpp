@@ -397,7 +397,13 @@ int aesgpu_pipeline_run(aesgpu_pipeline *pl, const aesgpu_key *key, const aesgpu
         const int fs = finish(pl, pl->slots[(c + k) % n_slots], dst);
         if (st == AESGPU_OK) st = fs;
     }
-    if (st != AESGPU_OK) (void)hipGetLastError();
+    if (st != AESGPU_OK) {
+        // A chunk that failed part way may have left a copy or a kernel on
+        // its stream that no event covers; none may touch the caller's
+        // buffers after the call returns.
+        for (Slot &s : pl->slots) (void)hipStreamSynchronize(s.stream);
+        (void)hipGetLastError();
+    }
     return st;
 }
 

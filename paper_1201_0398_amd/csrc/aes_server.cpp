@@ -194,6 +194,7 @@ struct aesgpu_server {
     std::vector<Slot> slots;
     std::thread worker;
     std::atomic<bool> stop{false};
+    uint64_t wake_gen = 0;  // bumped by every submission and release (under mu)
     int fatal = AESGPU_OK;
 
     aesgpu_server_stats stats{};
@@ -347,6 +348,7 @@ void worker_main(aesgpu_server *s) {
         s->fatal = AESGPU_EHIP;
         return;
     }
+    uint64_t seen_gen = 0;  // wake_gen at the last admission attempt
     while (!s->stop.load(std::memory_order_acquire)) {
         bool in_flight = false;
         // 1. Completions.
@@ -367,6 +369,7 @@ void worker_main(aesgpu_server *s) {
             bool backlog = false;
             {
                 std::lock_guard<std::mutex> g(s->mu);
+                seen_gen = s->wake_gen;
                 uint64_t bytes = 0;
                 while (!s->waiting.empty()) {
                     Req &r = s->waiting.front();
@@ -388,6 +391,10 @@ void worker_main(aesgpu_server *s) {
             const double t = s->now();
             for (Req &r : slot.reqs) r.t_launch = t;
             const int st = launch_slot(s, slot, backlog);
+            // A failed launch may have queued work that reads the staging
+            // buffers or writes the arena: let it end before the requests
+            // complete (and their outputs can be released and reused).
+            if (st != AESGPU_OK) (void)hipStreamSynchronize(slot.stream);
             std::lock_guard<std::mutex> g(s->mu);
             s->stats.batches++;
             s->stats.max_batch_requests =
@@ -399,11 +406,12 @@ void worker_main(aesgpu_server *s) {
                 in_flight = true;
             }
         }
-        // 3. Idle: sleep until a submission or a release; busy: keep polling.
+        // 3. Idle: sleep until a submission or a release (requests that wait
+        // for arena memory need a release); busy: keep polling.
         if (!in_flight) {
             std::unique_lock<std::mutex> lk(s->mu);
             s->cv.wait_for(lk, std::chrono::milliseconds(2), [&] {
-                return s->stop.load() || !s->waiting.empty();
+                return s->stop.load() || s->wake_gen != seen_gen;
             });
         } else {
             std::this_thread::yield();
@@ -524,6 +532,7 @@ int aesgpu_server_submit(aesgpu_server *s, uint64_t req_id, int dir, uint32_t ke
     if (s->waiting.size() >= s->cfg.max_queued) return AESGPU_EAGAIN;
     s->waiting.push_back(Req{req_id, key_id, uint8_t(dir), d_in, n_bytes, t_arrival, 0, 0.0});
     s->stats.requests_submitted++;
+    s->wake_gen++;
     s->cv.notify_one();
     return AESGPU_OK;
 }
@@ -547,6 +556,7 @@ int aesgpu_server_release(aesgpu_server *s, const void *d_out, size_t n_bytes) {
     if (p < b || p - b >= s->cfg.arena_bytes) return AESGPU_EINVAL;
     std::lock_guard<std::mutex> g(s->mu);
     if (!s->arena.release(p - b, n_bytes)) return AESGPU_EINVAL;
+    s->wake_gen++;
     s->cv.notify_one();
     return AESGPU_OK;
 }
