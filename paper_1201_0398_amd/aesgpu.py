@@ -181,8 +181,10 @@ def _check(status: int, what: str) -> int:
     return status
 
 
-def _ptr(x) -> int | None:
-    """Device address of a tensor (or an integer address as given)."""
+def _ptr(x, need: int = 0) -> int | None:
+    """Device address of a tensor (or an integer address as given).  A tensor
+    must hold at least ``need`` bytes: the library takes plain pointers and
+    cannot see a buffer's end, so a short tensor is refused here."""
     if x is None:
         return None
     if isinstance(x, int):
@@ -192,6 +194,8 @@ def _ptr(x) -> int | None:
             raise ValueError("buffer must be a device tensor")
         if not x.is_contiguous():
             raise ValueError("buffer must be contiguous")
+        if _nbytes(x) < need:
+            raise ValueError(f"buffer holds {_nbytes(x)} bytes, the call needs {need}")
         return x.data_ptr()
     raise TypeError(f"expected a device tensor or an address, got {type(x)}")
 
@@ -253,7 +257,8 @@ def aesgpu_ecb_encrypt(ctx, key: aesgpu_key, d_in, d_out, n_blocks: int | None =
                        stream=None, check: bool = True) -> int:
     if n_blocks is None:
         n_blocks = _nbytes(d_in) // 16
-    st = _lib.aesgpu_ecb_encrypt(ctx, ctypes.byref(key), _ptr(d_in), _ptr(d_out), n_blocks,
+    st = _lib.aesgpu_ecb_encrypt(ctx, ctypes.byref(key), _ptr(d_in, 16 * n_blocks),
+                                 _ptr(d_out, 16 * n_blocks), n_blocks,
                                  _stream(stream))
     return _check(st, "aesgpu_ecb_encrypt") if check else st
 
@@ -262,7 +267,8 @@ def aesgpu_ecb_decrypt(ctx, key: aesgpu_key, d_in, d_out, n_blocks: int | None =
                        stream=None, check: bool = True) -> int:
     if n_blocks is None:
         n_blocks = _nbytes(d_in) // 16
-    st = _lib.aesgpu_ecb_decrypt(ctx, ctypes.byref(key), _ptr(d_in), _ptr(d_out), n_blocks,
+    st = _lib.aesgpu_ecb_decrypt(ctx, ctypes.byref(key), _ptr(d_in, 16 * n_blocks),
+                                 _ptr(d_out, 16 * n_blocks), n_blocks,
                                  _stream(stream))
     return _check(st, "aesgpu_ecb_decrypt") if check else st
 
@@ -271,8 +277,9 @@ def aesgpu_ctr_xcrypt(ctx, key: aesgpu_key, nonce, ctr0: int, d_in, d_out,
                       n_bytes: int | None = None, stream=None, check: bool = True) -> int:
     if n_bytes is None:
         n_bytes = _nbytes(d_in)
-    st = _lib.aesgpu_ctr_xcrypt(ctx, ctypes.byref(key), _u8buf(nonce, 12), ctr0, _ptr(d_in),
-                                _ptr(d_out), n_bytes, _stream(stream))
+    st = _lib.aesgpu_ctr_xcrypt(ctx, ctypes.byref(key), _u8buf(nonce, 12), ctr0,
+                                _ptr(d_in, n_bytes), _ptr(d_out, n_bytes), n_bytes,
+                                _stream(stream))
     return _check(st, "aesgpu_ctr_xcrypt") if check else st
 
 
@@ -281,7 +288,8 @@ def aesgpu_ctr_le128_xcrypt(ctx, key: aesgpu_key, iv, index0: int, d_in, d_out,
     if n_bytes is None:
         n_bytes = _nbytes(d_in)
     st = _lib.aesgpu_ctr_le128_xcrypt(ctx, ctypes.byref(key), _u8buf(iv, 16), index0,
-                                      _ptr(d_in), _ptr(d_out), n_bytes, _stream(stream))
+                                      _ptr(d_in, n_bytes), _ptr(d_out, n_bytes), n_bytes,
+                                      _stream(stream))
     return _check(st, "aesgpu_ctr_le128_xcrypt") if check else st
 
 
@@ -289,8 +297,9 @@ def aesgpu_cbc_decrypt(ctx, key: aesgpu_key, iv, d_in, d_out, n_blocks: int | No
                        stream=None, check: bool = True) -> int:
     if n_blocks is None:
         n_blocks = _nbytes(d_in) // 16
-    st = _lib.aesgpu_cbc_decrypt(ctx, ctypes.byref(key), _u8buf(iv, 16), _ptr(d_in),
-                                 _ptr(d_out), n_blocks, _stream(stream))
+    st = _lib.aesgpu_cbc_decrypt(ctx, ctypes.byref(key), _u8buf(iv, 16),
+                                 _ptr(d_in, 16 * n_blocks), _ptr(d_out, 16 * n_blocks),
+                                 n_blocks, _stream(stream))
     return _check(st, "aesgpu_cbc_decrypt") if check else st
 
 
@@ -344,8 +353,9 @@ def aesgpu_batch_run(plan, d_keys, n_key_slots: int, d_in, d_out, in_bytes: int 
         in_bytes = _nbytes(d_in)
     if out_bytes is None:
         out_bytes = _nbytes(d_out)
-    st = _lib.aesgpu_batch_run(plan, _ptr(d_keys), n_key_slots, _ptr(d_in), in_bytes,
-                               _ptr(d_out), out_bytes, _stream(stream))
+    st = _lib.aesgpu_batch_run(plan, _ptr(d_keys, 32 * n_key_slots), n_key_slots,
+                               _ptr(d_in, in_bytes), in_bytes, _ptr(d_out, out_bytes),
+                               out_bytes, _stream(stream))
     return _check(st, "aesgpu_batch_run") if check else st
 
 
@@ -426,7 +436,8 @@ def aesgpu_server_submit(server, req_id: int, dir: int, key_id: int, d_in, n_byt
         n_bytes = _nbytes(d_in)
     if t_arrival is None:
         t_arrival = aesgpu_server_now(server)
-    st = _lib.aesgpu_server_submit(server, req_id, dir, key_id, _ptr(d_in), n_bytes, t_arrival)
+    st = _lib.aesgpu_server_submit(server, req_id, dir, key_id, _ptr(d_in, n_bytes), n_bytes,
+                                   t_arrival)
     return _check(st, "aesgpu_server_submit") if check else st
 
 
@@ -494,14 +505,17 @@ def aesgpu_host_free(addr: int, check: bool = True) -> int:
     return _check(st, "aesgpu_host_free") if check else st
 
 
-def _host_ptr(x) -> int | None:
-    """Host address of a contiguous numpy array (or an integer address)."""
+def _host_ptr(x, need: int = 0) -> int | None:
+    """Host address of a contiguous numpy array of at least ``need`` bytes
+    (or an integer address)."""
     if x is None or isinstance(x, int):
         return x
     import numpy as np
     if isinstance(x, np.ndarray):
         if not x.flags["C_CONTIGUOUS"]:
             raise ValueError("host buffer must be contiguous")
+        if x.nbytes < need:
+            raise ValueError(f"host buffer holds {x.nbytes} bytes, the call needs {need}")
         return x.ctypes.data
     raise TypeError(f"expected a numpy array or an address, got {type(x)}")
 
@@ -531,8 +545,8 @@ def aesgpu_pipeline_run(pl, key: aesgpu_key, op: aesgpu_host_op, h_in, h_out,
                         n_bytes: int | None = None, check: bool = True) -> int:
     if n_bytes is None:
         n_bytes = h_in.nbytes
-    st = _lib.aesgpu_pipeline_run(pl, ctypes.byref(key), ctypes.byref(op), _host_ptr(h_in),
-                                  _host_ptr(h_out), n_bytes)
+    st = _lib.aesgpu_pipeline_run(pl, ctypes.byref(key), ctypes.byref(op),
+                                  _host_ptr(h_in, n_bytes), _host_ptr(h_out, n_bytes), n_bytes)
     return _check(st, "aesgpu_pipeline_run") if check else st
 
 

@@ -249,6 +249,10 @@ def test_in_place_and_round_trip(A, ctx):
         A.aesgpu_batch_free(pd)
 
 
+def _nb(t):
+    return t.numel() * t.element_size()
+
+
 def test_plan_and_run_errors(A, ctx):
     import torch
     rng = np.random.default_rng(43)
@@ -268,6 +272,13 @@ def test_plan_and_run_errors(A, ctx):
                                   check=False) == A.AESGPU_EINVAL
         assert A.aesgpu_batch_run(ok, d_keys, 8, d_in.data_ptr() + 8, d_out,
                                   in_bytes=b["total"] - 8, check=False) == A.AESGPU_EALIGN
+        # sizes beyond the tensors are refused by the binding
+        with pytest.raises(ValueError):
+            A.aesgpu_batch_run(ok, d_keys, 9, d_in, d_out)
+        with pytest.raises(ValueError):
+            A.aesgpu_batch_run(ok, d_keys, 8, d_in, d_out, in_bytes=_nb(d_in) + 16)
+        with pytest.raises(ValueError):
+            A.aesgpu_batch_run(ok, d_keys, 8, d_in, d_out, out_bytes=_nb(d_out) + 16)
     finally:
         A.aesgpu_batch_free(ok)
     bad = A.make_msgs([0], [0], [32], [0], [130], [0], [0])

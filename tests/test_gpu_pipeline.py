@@ -218,6 +218,8 @@ def test_pipeline_errors(A, ctx):
         assert run(A.make_host_op(A.AESGPU_OP_CTR, ctr0=(1 << 32) - 2), buf, other, 48) == \
             A.AESGPU_ECTR_OVERFLOW
         assert run(A.make_host_op(A.AESGPU_OP_CTR), buf, other, 0) == A.AESGPU_OK
+        with pytest.raises(ValueError):                     # longer than the arrays
+            run(A.make_host_op(A.AESGPU_OP_ECB_ENCRYPT), buf, other[:2048], 4096)
         assert A.aesgpu_host_free(buf.ctypes.data, check=False) == A.AESGPU_EINVAL
         # A pinned range that is not 16-byte aligned takes the staged path.
         addr, pb = A.aesgpu_host_alloc(4096 + 64)

@@ -280,6 +280,27 @@ def test_argument_errors(A, ctx):
     assert (from_dev(d) == 0).all(), "a rejected call touched memory"
 
 
+def test_binding_refuses_short_tensors(A, ctx):
+    """The library takes plain pointers; the binding refuses a tensor
+    shorter than the size a call names before anything is launched."""
+    import torch
+    k = A.aesgpu_expand_key(bytes(16))
+    a = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    b = torch.zeros(256, dtype=torch.uint8, device="cuda")
+    calls = [
+        lambda: A.aesgpu_ecb_encrypt(ctx, k, a, b, 17),
+        lambda: A.aesgpu_ecb_decrypt(ctx, k, a, b[:64], 16),
+        lambda: A.aesgpu_ctr_xcrypt(ctx, k, bytes(12), 1, a, b, 257),
+        lambda: A.aesgpu_ctr_le128_xcrypt(ctx, k, bytes(16), 0, a[:100], b, 101),
+        lambda: A.aesgpu_cbc_decrypt(ctx, k, bytes(16), a, b, 20),
+    ]
+    for call in calls:
+        with pytest.raises(ValueError):
+            call()
+    torch.cuda.synchronize()
+    assert (from_dev(a) == 0).all() and (from_dev(b) == 0).all()
+
+
 def test_side_stream(A, ctx):
     import torch
     rng = np.random.default_rng(9)
