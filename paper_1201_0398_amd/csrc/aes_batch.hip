@@ -637,21 +637,32 @@ int enqueue_t(const BatchLaunch &L, hipStream_t s) {
     BatchParams p{L.msgs,     {L.tiles[0], L.tiles[1]}, {L.n_tiles[0], L.n_tiles[1]},
                   L.counters, fwd,  {n_static[0], n_static[1]}, {pull[0], pull[1]},
                   L.keys,     L.sched, L.in, L.out, L.tables, L.cbc_list, L.cbc_dummy};
-    if (L.n_tiles[0] + L.n_tiles[1])
-        hipLaunchKernelGGL((batch_kernel<BPL>), dim3(grid), dim3(kWG), 0, s, p);
+    // Each launch's own status (the thread's last-error state may hold an
+    // earlier, unrelated failure).
+    if (L.n_tiles[0] + L.n_tiles[1]) {
+        void *args[] = {&p};
+        if (hipLaunchKernel(reinterpret_cast<const void *>(&batch_kernel<BPL>), dim3(grid),
+                            dim3(kWG), args, 0, s) != hipSuccess)
+            return AESGPU_EHIP;
+    }
     if (L.n_cbc_groups) {
         const uint32_t n_cu = uint32_t(L.n_cu);
-        if (L.n_cbc_groups <= 4 * n_cu) {
-            const uint32_t g = (L.n_cbc_groups + 3) / 4;
-            hipLaunchKernelGGL(cbc_encrypt_kernel<256>, dim3(g), dim3(256), 0, s, p,
-                               L.cbc_groups, L.n_cbc_groups);
+        const Tile *groups = L.cbc_groups;
+        uint32_t n_groups = L.n_cbc_groups;
+        void *args[] = {&p, &groups, &n_groups};
+        hipError_t e;
+        if (n_groups <= 4 * n_cu) {
+            const uint32_t g = (n_groups + 3) / 4;
+            e = hipLaunchKernel(reinterpret_cast<const void *>(&cbc_encrypt_kernel<256>), dim3(g),
+                                dim3(256), args, 0, s);
         } else {
-            const uint32_t g = std::min<uint32_t>((L.n_cbc_groups + 15) / 16, n_cu);
-            hipLaunchKernelGGL(cbc_encrypt_kernel<kWG>, dim3(g), dim3(kWG), 0, s, p,
-                               L.cbc_groups, L.n_cbc_groups);
+            const uint32_t g = std::min<uint32_t>((n_groups + 15) / 16, n_cu);
+            e = hipLaunchKernel(reinterpret_cast<const void *>(&cbc_encrypt_kernel<kWG>), dim3(g),
+                                dim3(kWG), args, 0, s);
         }
+        if (e != hipSuccess) return AESGPU_EHIP;
     }
-    return hipGetLastError() == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
+    return AESGPU_OK;
 }
 
 }  // namespace

@@ -351,8 +351,13 @@ int launch_one(Params p, int n_cu, hipStream_t stream) {
     const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
     const uint64_t tiles = (v_end + uint64_t(kWG) * BPL - 1) / (uint64_t(kWG) * BPL);
     const uint32_t grid = tiles == 0 ? 1u : uint32_t(tiles < uint64_t(n_cu) ? tiles : uint64_t(n_cu));
-    hipLaunchKernelGGL((aes_kernel<OP, NR, BPL>), dim3(grid), dim3(kWG), 0, stream, p);
-    return hipGetLastError() == hipSuccess ? AESGPU_OK : AESGPU_EHIP;
+    // The launch's own status (the thread's last-error state may hold an
+    // earlier, unrelated failure).
+    void *args[] = {&p};
+    return hipLaunchKernel(reinterpret_cast<const void *>(&aes_kernel<OP, NR, BPL>), dim3(grid),
+                           dim3(kWG), args, 0, stream) == hipSuccess
+               ? AESGPU_OK
+               : AESGPU_EHIP;
 }
 
 template <Op OP, int BPL>
