@@ -207,13 +207,15 @@ def batched_bench(torch, A, ctx, rates: dict, reps: int, warm_s: float) -> dict:
                         "persistent launch with device key expansion, hipGraph replay"}
 
 
-def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None) -> dict:
+def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None, flags: int = 0,
+                  at_rates: list | None = None) -> dict:
     """Poisson arrivals of ECB requests (64 B..16 MiB log-uniform, half encrypt,
     half decrypt, keys from a resident pool of 1,024), replayed natively
     against the continuous-batching server at fractions of its measured
-    saturation rate.  With the single-buffer rates, the saturation time is
-    also compared with every request at the 1 GiB single-buffer rate of its
-    key size and direction."""
+    saturation rate (or at the request rates `at_rates`, to compare two
+    server modes at equal load).  With the single-buffer rates, the
+    saturation time is also compared with every request at the 1 GiB
+    single-buffer rate of its key size and direction."""
     import numpy as np
 
     from paper_1201_0398_amd import workloads
@@ -227,7 +229,8 @@ def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None) -> 
     total = int(tr.sizes.sum())
     src = torch.from_numpy(tr.source.copy()).to("cuda")
     ptrs = src.data_ptr() + tr.src_offsets
-    server = A.aesgpu_server_create(ctx, tr.pool_keys, tr.pool_bits, arena_bytes=arena)
+    server = A.aesgpu_server_create(ctx, tr.pool_keys, tr.pool_bits, arena_bytes=arena,
+                                    flags=flags)
 
     def replay(arrivals):
         reqs = A.make_requests(arrivals, ptrs, tr.sizes, tr.key_ids, tr.dirs)
@@ -242,8 +245,10 @@ def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None) -> 
     lat, span = replay(np.zeros(n_requests))
     lam_sat = n_requests / span
     points = []
-    for frac in (0.1, 0.25, 0.5, 0.7, 0.85, 0.95):
-        lam = frac * lam_sat
+    fracs = (0.1, 0.25, 0.5, 0.7, 0.85, 0.95)
+    for i, frac in enumerate(fracs):
+        lam = at_rates[i] if at_rates else frac * lam_sat
+        frac = lam / lam_sat
         # Three replays per point: the median of each figure, and the worst
         # replay's p99 and lowest throughput beside it.
         p50, p99, gbs = [], [], []
@@ -252,7 +257,7 @@ def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None) -> 
             p50.append(float(np.median(lat)) * 1e6)
             p99.append(float(np.quantile(lat, 0.99)) * 1e6)
             gbs.append(total / span / 1e9)
-        points.append({"frac_of_saturation": frac, "rate_req_s": round(lam, 1),
+        points.append({"frac_of_saturation": round(frac, 3), "rate_req_s": round(lam, 1),
                        "p50_us": round(float(np.median(p50)), 1),
                        "p99_us": round(float(np.median(p99)), 1),
                        "GB_s": round(float(np.median(gbs)), 1),
@@ -548,6 +553,15 @@ def main() -> int:
     if not args.no_serving:
         out["serving"] = serving_bench(torch, A, ctx, args.serve_requests,
                                        None if args.no_batched else rates)
+        # The resident kernel at the same request rates, then its own saturation.
+        out["serving_resident"] = serving_bench(
+            torch, A, ctx, args.serve_requests, None if args.no_batched else rates,
+            flags=A.AESGPU_SERVER_RESIDENT,
+            at_rates=[p["rate_req_s"] for p in out["serving"]["points"]])
+        out["serving_resident"]["mode"] = (
+            "one resident kernel fed from rings in pinned host memory, at the same request "
+            "rates as the batched server's points; frac_of_saturation is against the resident "
+            "kernel's own saturation")
     if not args.no_cbc_batch:
         out["batched_cbc"] = cbc_batch_bench(torch, A, ctx, args.batched_reps, args.min_warmup_s)
     if not args.no_pipeline:

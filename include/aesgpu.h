@@ -351,9 +351,11 @@ typedef struct {
                                     waiting behind them, run as one single-buffer launch
                                     per request (0 = 4, at most 16;
                                     AESGPU_SERVER_NO_DIRECT: always the batched kernel) */
+    uint32_t flags;              /* 0 or AESGPU_SERVER_RESIDENT */
 } aesgpu_server_config;
 
 #define AESGPU_SERVER_NO_DIRECT 0xFFFFFFFFu
+#define AESGPU_SERVER_RESIDENT 1u   /* one kernel stays on the GPU and takes the tiles */
 
 /* A finished request.  d_out points into the server's arena and stays valid
  * until aesgpu_server_release().  Times are seconds on the server clock
@@ -402,6 +404,22 @@ typedef struct {
  * direct_requests requests, when no other request is waiting, instead runs as
  * one single-buffer kernel per request with the round keys as kernel
  * arguments, which saves the upload.
+ *
+ * With AESGPU_SERVER_RESIDENT in flags there are no per-batch launches: one
+ * kernel stays on the GPU (one workgroup per CU, half of them holding the
+ * encryption tables and half the decryption tables) and takes tiles from two
+ * rings in pinned host memory, which the dispatcher fills as it admits
+ * requests (tiles sized so that a request spreads over the waves that the
+ * requests already in flight leave free).  The kernel reports each finished
+ * request through a flag in pinned memory.  It ends by itself after tens of
+ * milliseconds without new tiles and is launched again when requests come;
+ * aesgpu_server_destroy() stops it.  While it runs it holds every CU's LDS,
+ * so other kernels on the device run only in the registers and waves it
+ * leaves free (kernels that need LDS wait for it to end), and it holds the
+ * hardware queue of its stream: work of other streams that the runtime maps
+ * to the same hardware queue waits for it too.  n_streams, direct_requests
+ * and the max_batch_* limits do not apply; at most 65,536 requests are in
+ * flight, and stats.batches counts the kernel's launches.
  * Errors: EINVAL, EKEYLEN, ENOMEM, EHIP.
  */
 int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *key_bits,

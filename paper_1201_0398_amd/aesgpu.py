@@ -49,6 +49,7 @@ AESGPU_DIR_ENCRYPT = 0
 AESGPU_DIR_DECRYPT = 1
 AESGPU_BATCH_NO_GRAPH = 1
 AESGPU_SERVER_NO_DIRECT = 0xFFFFFFFF
+AESGPU_SERVER_RESIDENT = 1
 
 
 class aesgpu_msg(ctypes.Structure):
@@ -75,7 +76,8 @@ class aesgpu_server_config(ctypes.Structure):
     _fields_ = [("arena_bytes", ctypes.c_uint64), ("n_streams", ctypes.c_uint32),
                 ("blocks_per_lane", ctypes.c_uint32), ("tile_blocks", ctypes.c_uint32),
                 ("max_batch_requests", ctypes.c_uint32), ("max_batch_bytes", ctypes.c_uint64),
-                ("max_queued", ctypes.c_uint32), ("direct_requests", ctypes.c_uint32)]
+                ("max_queued", ctypes.c_uint32), ("direct_requests", ctypes.c_uint32),
+                ("flags", ctypes.c_uint32)]
 
 
 class aesgpu_done(ctypes.Structure):
@@ -409,7 +411,7 @@ def aesgpu_arena_destroy(arena) -> None:
 def aesgpu_server_create(ctx, keys, key_bits, arena_bytes: int, n_streams: int = 0,
                          blocks_per_lane: int = 0, tile_blocks: int = 0,
                          max_batch_requests: int = 0, max_batch_bytes: int = 0,
-                         max_queued: int = 0, direct_requests: int = 0):
+                         max_queued: int = 0, direct_requests: int = 0, flags: int = 0):
     """keys: (n, 32) uint8 host array (key bytes first); key_bits: n sizes."""
     import numpy as np
     k = np.ascontiguousarray(keys, dtype=np.uint8).reshape(-1, 32)
@@ -417,7 +419,7 @@ def aesgpu_server_create(ctx, keys, key_bits, arena_bytes: int, n_streams: int =
     assert bits.size == k.shape[0]
     cfg = aesgpu_server_config(arena_bytes, n_streams, blocks_per_lane, tile_blocks,
                                max_batch_requests, max_batch_bytes, max_queued,
-                               direct_requests)
+                               direct_requests, flags)
     h = ctypes.c_void_p()
     _check(_lib.aesgpu_server_create(ctx, k.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)),
                                      bits.ctypes.data_as(ctypes.POINTER(ctypes.c_uint16)),

@@ -91,4 +91,58 @@ int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vec
 // messages) the CBC-encryption launch.
 int enqueue_batch(const BatchLaunch &L, hipStream_t stream);
 
+// ---- resident serving kernel ----------------------------------------------------
+//
+// One ECB tile of a served request, written by the host into a ring in
+// pinned host memory and read by the kernel over the host link.
+struct alignas(64) ResTile {
+    uint64_t in;        // device address of the tile's first input block
+    uint64_t out;       // device address of its first output block
+    uint32_t n_blocks;  // blocks in this tile
+    uint32_t key_slot;
+    uint32_t nr;
+    uint32_t req_slot;  // the request's slot (tile counter, completion entry)
+    uint32_t target;    // the slot's tile count (mod 2^32) once the request is done
+    uint32_t pad[7];
+};
+static_assert(sizeof(ResTile) == 64, "resident tile layout");
+
+// Host control words (pinned, written by the host): published tail of each
+// ring (tiles 0 .. tail - 1 are valid), then the stop request.
+constexpr uint32_t kResHostWords = 3;
+
+// Device control block, in 64-bit words, each group on a 128-byte line of its
+// own: the ticket counter of each set at word 16 * set, the count of finished
+// requests at word 32 and the count of waves that have ended at word 40,
+// workgroup w's copy of its set's tail at word 48 + 16 * w and its stop word
+// (the launch epoch that must stop) right after it.  Zero before the first
+// launch.
+constexpr size_t kResDoneWord = 32;
+constexpr size_t kResExitWord = 40;
+constexpr size_t kResCopyWord = 48;
+constexpr size_t res_dev_words(uint32_t n_wg) { return kResCopyWord + 16 * size_t(n_wg); }
+
+struct ResidentLaunch {
+    const ResTile *ring[2];     // device addresses of the two host rings
+    uint64_t ring_mask;         // ring entries - 1 (a power of two)
+    const uint64_t *host_ctl;   // device address of the host control words
+    uint64_t *dev;              // device control block
+    uint32_t *tiles_done;       // per request slot: tiles finished, only grows (mod 2^32)
+    uint64_t *done_ring;        // device address of the host completion ring: entry
+                                // i % (done_mask + 1) = (i + 1) << 32 | slot, written
+                                // once the i-th request (in finishing order) is done
+    uint64_t done_mask;
+    const uint32_t *sched;      // resident schedules (kSchedWords per key slot)
+    const uint32_t *tables;
+    uint32_t n_wg;              // workgroups (one per CU at most)
+    uint32_t n_wg_forward;      // the first n_wg_forward serve ring 0 (forward tables)
+    uint32_t bpl;
+    uint32_t epoch;             // launch number, distinguishes stop requests
+    uint32_t idle_polls;        // polls without work before the kernel ends
+};
+
+// Launches the resident kernel; it ends when the host sets the stop word or
+// after idle_polls polls without new work.
+int launch_resident(const ResidentLaunch &L, hipStream_t stream);
+
 }  // namespace aesgpu

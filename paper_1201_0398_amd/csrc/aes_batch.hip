@@ -179,11 +179,30 @@ __device__ __forceinline__ void counter_round1(const uint32_t *lds, const Bases 
     s[3] = cc.p[3] ^ tlook<0>(lds, w3, b.t[0]);
 }
 
+// Block loads and stores of a tile with a cache policy: 0 (the default) for
+// launches, whose start and end make memory coherent; kCoherent for the
+// resident kernel, whose tiles must see inputs and publish outputs
+// device-wide without L2 invalidations or write-backs (sc1: agent-coherent
+// accesses).
+constexpr int kCoherent = 16;
+
+template <int kPolicy>
+__device__ __forceinline__ uint4 tile_load16(rsrc_t r, uint32_t offset) {
+    const u32x4 x = __builtin_amdgcn_raw_buffer_load_b128(r, offset, 0, kPolicy);
+    return make_uint4(x[0], x[1], x[2], x[3]);
+}
+
+template <int kPolicy>
+__device__ __forceinline__ void tile_store16(rsrc_t r, uint32_t offset, const uint4 &v) {
+    const u32x4 x = {v.x, v.y, v.z, v.w};
+    __builtin_amdgcn_raw_buffer_store_b128(x, r, offset, 0, kPolicy);
+}
+
 // One tile: nr rounds on BPL blocks per lane per step.  The round loop is not
 // unrolled and takes nr at run time: one short loop body serves all key
 // sizes, so the code a workgroup runs fits the instruction cache even when
 // each CU executes it only once (small batches).
-template <bool kInv, int BPL>
+template <bool kInv, int BPL, int kPolicy = 0>
 __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, const BatchParams &p,
                                          const DevMsg &m, const Tile &tile) {
     const uint32_t nr = m.nr;
@@ -248,11 +267,11 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     const uint32_t cbc_mask = cbc ? ~0u : 0u;
     uint4 next[BPL], next_prev[BPL];
 #pragma unroll
-    for (int j = 0; j < BPL; ++j) next[j] = buffer_load16(rin, (uint32_t(j) * 64u + lane) * 16u);
+    for (int j = 0; j < BPL; ++j) next[j] = tile_load16<kPolicy>(rin, (uint32_t(j) * 64u + lane) * 16u);
     if constexpr (kInv) {
 #pragma unroll
         for (int j = 0; j < BPL; ++j)
-            next_prev[j] = buffer_load16(rprev, (uint32_t(j) * 64u + lane - pshift) * 16u);
+            next_prev[j] = tile_load16<kPolicy>(rprev, (uint32_t(j) * 64u + lane - pshift) * 16u);
     }
     {
         // In the loop a step's loads are followed by the previous step's
@@ -262,7 +281,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
         const rsrc_t none = buffer_rsrc(out, 0);
 #pragma unroll
         for (int j = 0; j < BPL; ++j)
-            buffer_store16(none, (uint32_t(j) * 64u + lane) * 16u, make_uint4(0, 0, 0, 0));
+            tile_store16<kPolicy>(none, (uint32_t(j) * 64u + lane) * 16u, make_uint4(0, 0, 0, 0));
     }
     for (uint64_t base = first; base < lim; base += kStep) {
         // Keep the round-key reads inside the loop: hoisting all of them would
@@ -276,13 +295,13 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             d[j] = next[j];
-            next[j] = buffer_load16(rin, (step_off + kStep + uint32_t(j) * 64u + lane) * 16u);
+            next[j] = tile_load16<kPolicy>(rin, (step_off + kStep + uint32_t(j) * 64u + lane) * 16u);
         }
         if constexpr (kInv) {
 #pragma unroll
             for (int j = 0; j < BPL; ++j) {
                 prev[j] = next_prev[j];
-                next_prev[j] = buffer_load16(
+                next_prev[j] = tile_load16<kPolicy>(
                     rprev, (step_off + kStep + uint32_t(j) * 64u + lane - pshift) * 16u);
             }
         }
@@ -333,7 +352,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                 o.z ^= (b0 ? m.nonce[2] : prev[j].z) & cbc_mask;
                 o.w ^= (b0 ? m.ctr0 : prev[j].w) & cbc_mask;
             }
-            buffer_store16(rout, (step_off + uint32_t(j) * 64u + lane) * 16u, o);
+            tile_store16<kPolicy>(rout, (step_off + uint32_t(j) * 64u + lane) * 16u, o);
         }
     }
     if constexpr (!kInv) {
@@ -607,6 +626,221 @@ __global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
     }
 }
 
+// ---- resident serving kernel ---------------------------------------------------
+//
+// The kernel stays on the GPU while requests keep coming: the host writes
+// tile records into two rings in pinned host memory (ring 0 for the forward
+// tables, ring 1 for the inverse tables) and publishes each ring's tail;
+// workgroups below n_wg_forward serve ring 0, the others ring 1, each with
+// its table set staged once.  Wave 0 of the first workgroup of each set reads
+// the host's tail and stop words over the link and copies the tail to one
+// word per workgroup of its set; the other waves watch their workgroup's copy.
+// A wave takes tiles by tickets: one fetch-and-add on its set's claim counter
+// (a compare-and-swap there serialises thousands of waves), taken only while
+// the copy shows tiles that no ticket covers yet.  A ticket may run ahead of
+// the published tail: its wave then waits for the host to publish that tile,
+// so at most one ticket per wave is ahead.  The wave that counts a request's
+// last tile (each request slot has a tile counter that only grows; a record
+// carries the count that completes its request) appends the slot to a
+// completion ring in host memory, each entry tagged with its position so
+// that the host reads the ring in order.
+// Every wave ends: the poller after the host's stop word or idle_polls polls
+// without a new tail (it then posts the launch epoch in every stop word of its
+// set), a worker once its set's stop word holds the epoch (after serving a
+// ticket that is published by then), or after 4 * idle_polls idle polls of
+// its own (64 * idle_polls while it holds a ticket).  The last wave to end points each claim
+// counter back at the first tile that no wave served (tickets that ran ahead
+// and were never published), so the next launch starts there.
+
+constexpr uint64_t kNoTile = ~0ull;
+
+__device__ __forceinline__ uint64_t uniform64(uint64_t v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane(uint32_t(v));
+    const uint32_t hi = __builtin_amdgcn_readfirstlane(uint32_t(v >> 32));
+    return (uint64_t(hi) << 32) | lo;
+}
+
+// A tile record from host memory: lanes 0..15 read one word each, bypassing
+// the caches (ring entries are rewritten by the host), then every field is
+// made wave-uniform.
+__device__ __forceinline__ ResTile load_record(const ResTile *r) {
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t *w = reinterpret_cast<uint32_t *>(const_cast<ResTile *>(r));
+    uint32_t v = 0;
+    if (lane < 16) v = __hip_atomic_load(w + lane, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    ResTile t;
+    uint32_t *d = reinterpret_cast<uint32_t *>(&t);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) d[i] = __builtin_amdgcn_readlane(v, i);
+    return t;
+}
+
+// The set's poller: the host tail and stop words, copied to the set's
+// workgroups.
+__device__ void poll_host(const ResidentLaunch &p, uint32_t set) {
+    const uint32_t lane = threadIdx.x & 63u;
+    const uint32_t wg0 = set ? p.n_wg_forward : 0u, wg1 = set ? p.n_wg : p.n_wg_forward;
+    uint64_t *host = const_cast<uint64_t *>(p.host_ctl);
+    uint64_t seen = 0;
+    uint32_t idle = 0;
+    for (;;) {
+        uint64_t h = 0, stop = 0;
+        // Relaxed loads that bypass the caches: the tile records are read
+        // the same way, so no acquire (an L2 invalidation) is needed here.
+        if (lane == 0) {
+            h = __hip_atomic_load(host + set, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            stop = __hip_atomic_load(host + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        h = uniform64(h);
+        stop = uniform64(stop);
+        if (h > seen) {
+            for (uint32_t w = wg0 + lane; w < wg1; w += 64)
+                __hip_atomic_store(p.dev + kResCopyWord + 16 * size_t(w), h, __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            seen = h;
+            idle = 0;
+        }
+        if (stop || ++idle > p.idle_polls) {
+            // Release: a worker that sees the stop word also sees every tail
+            // stored before it.
+            for (uint32_t w = wg0 + lane; w < wg1; w += 64)
+                __hip_atomic_store(p.dev + kResCopyWord + 16 * size_t(w) + 1,
+                                   uint64_t(p.epoch), __ATOMIC_RELEASE,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+            return;
+        }
+        __builtin_amdgcn_s_sleep(8);
+    }
+}
+
+// A worker wave of one set: take tickets, run and count tiles until told to
+// stop.
+template <bool kInv, int BPL>
+__device__ void serve_ring(const uint32_t *lds, const Bases &b, const ResidentLaunch &p) {
+    constexpr uint32_t set = kInv ? 1u : 0u;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint64_t *claimed = p.dev + 16 * set;
+    uint64_t *copy = p.dev + kResCopyWord + 16 * size_t(blockIdx.x);
+    BatchParams bp{};
+    bp.sched = p.sched;
+    bp.tables = p.tables;
+    uint64_t known = 0;         // tickets reached this tail when last taken
+    uint64_t ticket = kNoTile;  // this wave's tile, perhaps not yet published
+    uint32_t idle = 0;
+    for (;;) {
+        // Relaxed polls: an acquire at this scope invalidates the L2, which
+        // thousands of polling waves must not do.
+        uint64_t tl = 0, st = 0;
+        if (lane == 0) {
+            tl = __hip_atomic_load(copy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st = __hip_atomic_load(copy + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        tl = uniform64(tl);
+        st = uniform64(st);
+        if (st >= p.epoch) {
+            // Stopping: the tail stored before the stop word is visible now.
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            if (lane == 0) tl = __hip_atomic_load(copy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tl = uniform64(tl);
+            if (ticket == kNoTile || ticket >= tl) break;
+        }
+        if (ticket == kNoTile && tl > known) {
+            uint64_t t = 0;
+            if (lane == 0)
+                t = __hip_atomic_fetch_add(claimed, 1ull, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_AGENT);
+            ticket = uniform64(t);
+            if (ticket >= tl) known = tl;  // every published tile has a ticket
+        }
+        if (ticket != kNoTile && ticket < tl) {
+            idle = 0;
+            const ResTile r = load_record(p.ring[set] + (ticket & p.ring_mask));
+            ticket = kNoTile;
+            DevMsg m{};
+            m.in_off = r.in;     // absolute addresses: bp.in and bp.out are null
+            m.out_off = r.out;
+            m.n_full = r.n_blocks;
+            m.key_slot = r.key_slot;
+            m.nr = r.nr;
+            m.mode = AESGPU_MODE_ECB;
+            const Tile tile{0u, r.n_blocks, 0ull};
+            // Agent-coherent loads and stores: the tile reads its input as the
+            // producer left it and its output is visible device-wide once the
+            // stores are complete, with no L2 invalidation or write-back (a
+            // fence at this scope costs one per tile, and those serialise).
+            run_tile<kInv, BPL, kCoherent>(lds, b, bp, m, tile);
+            // The tile is counted once its stores are complete.  The slot's
+            // counter only grows (modulo 2^32); the record holds the count at
+            // which this request is complete, and the wave that reaches it
+            // reports the request to the host, which reads no output data.
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            if (lane == 0) {
+                const uint32_t n = __hip_atomic_fetch_add(p.tiles_done + r.req_slot, 1u,
+                                                          __ATOMIC_RELAXED,
+                                                          __HIP_MEMORY_SCOPE_AGENT) + 1u;
+                if (n == r.target) {
+                    const uint64_t i = __hip_atomic_fetch_add(p.dev + kResDoneWord, 1ull,
+                                                              __ATOMIC_RELAXED,
+                                                              __HIP_MEMORY_SCOPE_AGENT);
+                    __hip_atomic_store(p.done_ring + (i & p.done_mask),
+                                       ((i + 1) << 32) | r.req_slot, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_SYSTEM);
+                }
+            }
+            continue;
+        }
+        // A wave holding a ticket waits for its tile until the stop word; one
+        // without a ticket also ends after a long idle spell, and one with a
+        // ticket after a much longer one (a ticket given up that way is
+        // served after the next launch: the last wave out rewinds the
+        // counter to it).
+        if (++idle > (ticket == kNoTile ? 4u : 64u) * p.idle_polls) break;
+        if (ticket == kNoTile)
+            __builtin_amdgcn_s_sleep(32);
+        else
+            __builtin_amdgcn_s_sleep(2);
+    }
+}
+
+template <int BPL>
+__global__ __launch_bounds__(kWG) void resident_kernel(ResidentLaunch p) {
+    __shared__ uint32_t lds[kFwdWords + kInvSWords];
+    const Bases b = lane_bases();
+    const bool inv = blockIdx.x >= p.n_wg_forward;   // uniform over the workgroup
+    if (inv)
+        stage_tables<true>(lds, p.tables);
+    else
+        stage_tables<false>(lds, p.tables);
+    if ((threadIdx.x >> 6) == 0 && (blockIdx.x == 0 || blockIdx.x == p.n_wg_forward))
+        poll_host(p, inv ? 1u : 0u);
+    else if (inv)
+        serve_ring<true, BPL>(lds, b, p);
+    else
+        serve_ring<false, BPL>(lds, b, p);
+    // Count the wave out.  The last one points each claim counter at the
+    // first tile no wave served: tickets beyond the last published tail were
+    // never served, every ticket below it was.
+    if ((threadIdx.x & 63u) == 0) {
+        const uint64_t waves = uint64_t(gridDim.x) * (kWG / 64);
+        const uint64_t before = __hip_atomic_fetch_add(p.dev + kResExitWord, 1ull,
+                                                       __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (before == waves - 1) {
+            for (uint32_t set = 0; set < 2; ++set) {
+                const uint32_t wg = set ? p.n_wg_forward : 0u;
+                const uint64_t seen = __hip_atomic_load(p.dev + kResCopyWord + 16 * size_t(wg),
+                                                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                const uint64_t c = __hip_atomic_load(p.dev + 16 * set, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if (c > seen)
+                    __hip_atomic_store(p.dev + 16 * set, seen, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_AGENT);
+            }
+            __hip_atomic_store(p.dev + kResExitWord, 0ull, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
+}
+
 template <int BPL>
 int enqueue_t(const BatchLaunch &L, hipStream_t s) {
     const uint32_t total = L.n_tiles[0] + L.n_tiles[1];
@@ -669,6 +903,20 @@ int enqueue_t(const BatchLaunch &L, hipStream_t s) {
 
 int enqueue_batch(const BatchLaunch &L, hipStream_t s) {
     return L.bpl == 1 ? enqueue_t<1>(L, s) : L.bpl == 2 ? enqueue_t<2>(L, s) : enqueue_t<4>(L, s);
+}
+
+int launch_resident(const ResidentLaunch &L, hipStream_t s) {
+    if (L.n_wg < 2 || L.n_wg > 1024 || L.n_wg_forward == 0 || L.n_wg_forward >= L.n_wg ||
+        L.epoch == 0 || (L.ring_mask & (L.ring_mask + 1)) != 0 ||
+        (L.done_mask & (L.done_mask + 1)) != 0)
+        return AESGPU_EINVAL;
+    ResidentLaunch p = L;
+    void *args[] = {&p};
+    const void *fn = L.bpl == 1   ? reinterpret_cast<const void *>(&resident_kernel<1>)
+                     : L.bpl == 2 ? reinterpret_cast<const void *>(&resident_kernel<2>)
+                                  : reinterpret_cast<const void *>(&resident_kernel<4>);
+    return hipLaunchKernel(fn, dim3(L.n_wg), dim3(kWG), args, 0, s) == hipSuccess ? AESGPU_OK
+                                                                                 : AESGPU_EHIP;
 }
 
 int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vector<DevMsg> &dm,

@@ -174,6 +174,21 @@ struct Slot {
     std::vector<Req> reqs;
 };
 
+// Resident mode: a request's tiles and where they sit in their ring.
+struct Pub {
+    uint64_t first;   // ring index of the first tile
+    uint64_t n;       // tiles
+    bool done;
+};
+
+struct Live {
+    Req req;
+    uint32_t slot;    // tile counter and completion entry
+    uint32_t set;     // ring
+    uint64_t tile;    // blocks per tile
+    uint64_t pub;     // publication number within the ring
+};
+
 }  // namespace
 
 struct aesgpu_server {
@@ -198,6 +213,31 @@ struct aesgpu_server {
     int fatal = AESGPU_OK;
 
     aesgpu_server_stats stats{};
+
+    // Resident mode (AESGPU_SERVER_RESIDENT): one kernel stays on the GPU and
+    // takes tiles from two rings in pinned host memory.
+    bool resident = false;
+    uint64_t ring_cap = 0;                      // entries per ring (power of two)
+    ResTile *h_ring[2] = {nullptr, nullptr};    // host addresses
+    ResTile *d_ring[2] = {nullptr, nullptr};    // device addresses
+    uint64_t *h_ctl = nullptr, *d_ctl = nullptr;    // tails and stop word
+    uint64_t *h_done = nullptr, *d_done = nullptr;  // completion ring (kResSlots entries)
+    uint64_t done_head = 0;                     // completion entries consumed
+    uint64_t *d_dev = nullptr;                  // the kernel's control block
+    uint32_t *d_tiles_done = nullptr;           // per request slot
+    hipStream_t res_stream = nullptr;
+    hipEvent_t res_event = nullptr;
+    bool res_running = false;
+    uint32_t epoch = 0;
+    uint32_t n_wg = 0, n_wg_forward = 0;
+    uint64_t tail[2] = {0, 0};                  // published tiles per ring
+    std::deque<Pub> pubs[2];                    // unfinished publications, oldest first
+    uint64_t pub_base[2] = {0, 0};              // publication number of pubs[set].front()
+    uint64_t pub_count[2] = {0, 0};
+    std::vector<Live> live;                     // by slot: admitted, not yet complete
+    size_t n_live = 0;
+    std::vector<uint32_t> free_slots;
+    std::vector<uint32_t> slot_tiles;           // tiles ever counted per slot (mod 2^32)
 
     double now() const { return std::chrono::duration<double>(Clock::now() - t0).count(); }
 };
@@ -419,6 +459,217 @@ void worker_main(aesgpu_server *s) {
     }
 }
 
+// ---- resident mode ---------------------------------------------------------------
+
+constexpr uint64_t kResRing = uint64_t(1) << 16;   // tiles per ring
+constexpr uint32_t kResSlots = 1u << 16;           // requests in flight at most
+constexpr uint32_t kResIdlePolls = 25000;          // ≈ tens of ms without work, then the kernel ends
+
+// Blocks per tile of a request in the resident kernel: spread it over the
+// waves of its set that the requests already in flight leave free (a lone
+// request gets them all), whole steps of the kernel, between 256 blocks
+// and 8192, and never more tiles than half a ring.
+uint64_t resident_tile_blocks(const aesgpu_server *s, uint64_t n_blocks, uint64_t live_in_set) {
+    if (s->cfg.tile_blocks) return std::max<uint64_t>(s->cfg.tile_blocks,
+                                                      (n_blocks + kResRing / 2 - 1) / (kResRing / 2));
+    const uint64_t step = 64ull * s->cfg.blocks_per_lane;
+    const uint64_t waves = std::max<uint64_t>(1, uint64_t(s->n_wg / 2) * 16 - 1);
+    const uint64_t share = std::max<uint64_t>(1, waves / (1 + live_in_set));
+    uint64_t tb = (n_blocks + share - 1) / share;
+    tb = (tb + step - 1) / step * step;
+    tb = std::min<uint64_t>(std::max<uint64_t>(tb, std::max<uint64_t>(step, 256)), 8192);
+    return std::max<uint64_t>(tb, (n_blocks + kResRing / 2 - 1) / (kResRing / 2));
+}
+
+int launch_resident_kernel(aesgpu_server *s) {
+    ResidentLaunch L{};
+    L.ring[0] = s->d_ring[0];
+    L.ring[1] = s->d_ring[1];
+    L.ring_mask = s->ring_cap - 1;
+    L.host_ctl = s->d_ctl;
+    L.dev = s->d_dev;
+    L.tiles_done = s->d_tiles_done;
+    L.done_ring = s->d_done;
+    L.done_mask = kResSlots - 1;
+    L.sched = s->d_sched;
+    L.tables = s->ctx->d_tables;
+    L.n_wg = s->n_wg;
+    L.n_wg_forward = s->n_wg_forward;
+    L.bpl = s->cfg.blocks_per_lane;
+    L.epoch = ++s->epoch;
+    L.idle_polls = kResIdlePolls;
+    int st = launch_resident(L, s->res_stream);
+    if (st == AESGPU_OK && hipEventRecord(s->res_event, s->res_stream) != hipSuccess)
+        st = AESGPU_EHIP;
+    return st;
+}
+
+void worker_resident(aesgpu_server *s) {
+    if (hipSetDevice(s->ctx->device) != hipSuccess) {
+        std::lock_guard<std::mutex> g(s->mu);
+        s->fatal = AESGPU_EHIP;
+        return;
+    }
+    std::vector<Live> admitted;
+    std::vector<aesgpu_done> finished;
+    uint64_t seen_gen = 0;
+    uint64_t live_in_set[2] = {0, 0};
+    while (!s->stop.load(std::memory_order_acquire)) {
+        // 1. Completions: the kernel appends a request's slot to the
+        // completion ring once its last tile is stored; entry i carries the
+        // tag i + 1, so an entry not yet written (or from the ring's previous
+        // lap) is told apart.  At most kResSlots requests are in flight, so
+        // the kernel never overtakes this reader.
+        finished.clear();
+        const double t = s->now();
+        for (;;) {
+            const uint64_t e = __atomic_load_n(&s->h_done[s->done_head & (kResSlots - 1)],
+                                               __ATOMIC_ACQUIRE);
+            if (uint32_t(e >> 32) != uint32_t(s->done_head + 1)) break;
+            s->done_head++;
+            Live &l = s->live[uint32_t(e)];
+            aesgpu_done d{};
+            d.req_id = l.req.id;
+            d.status = AESGPU_OK;
+            d.d_out = s->d_arena + l.req.out_off;
+            d.n_bytes = l.req.n;
+            d.t_arrival = l.req.t_arrival;
+            d.t_launch = l.req.t_launch;
+            d.t_done = t;
+            finished.push_back(d);
+            s->pubs[l.set][l.pub - s->pub_base[l.set]].done = true;
+            s->free_slots.push_back(l.slot);
+            live_in_set[l.set]--;
+            s->n_live--;
+        }
+        for (int set = 0; set < 2; ++set) {
+            while (!s->pubs[set].empty() && s->pubs[set].front().done) {
+                s->pubs[set].pop_front();
+                s->pub_base[set]++;
+            }
+        }
+        // 2. Admission, in arrival order, while a request slot, ring space
+        // and arena memory are free.
+        admitted.clear();
+        {
+            std::lock_guard<std::mutex> g(s->mu);
+            for (const aesgpu_done &d : finished) {
+                s->completed.push_back(d);
+                s->stats.requests_done++;
+                s->stats.bytes_done += d.n_bytes;
+            }
+            seen_gen = s->wake_gen;
+            uint64_t planned[2] = {0, 0};  // tiles of requests admitted in this pass
+            while (!s->waiting.empty() && !s->free_slots.empty()) {
+                Req &r = s->waiting.front();
+                const uint32_t set = r.dir == AESGPU_DIR_DECRYPT ? 1u : 0u;
+                const uint64_t nb = r.n / 16;
+                const uint64_t tb = resident_tile_blocks(s, nb, live_in_set[set] + admitted.size());
+                const uint64_t k = (nb + tb - 1) / tb;
+                const uint64_t head = s->pubs[set].empty() ? s->tail[set] : s->pubs[set].front().first;
+                if (s->tail[set] + planned[set] + k - head > s->ring_cap) break;
+                uint64_t off = 0;
+                if (!s->arena.alloc(r.n, &off)) break;  // FIFO: wait for memory
+                r.out_off = off;
+                Live l{};
+                l.req = r;
+                l.slot = s->free_slots.back();
+                s->free_slots.pop_back();
+                l.set = set;
+                l.tile = tb;
+                admitted.push_back(l);
+                planned[set] += k;
+                s->waiting.pop_front();
+            }
+            if (!admitted.empty()) {
+                s->stats.max_batch_requests =
+                    std::max<uint64_t>(s->stats.max_batch_requests, admitted.size());
+            }
+        }
+        // 3. Publication: tile records first, then the tails.
+        if (!admitted.empty()) {
+            const double tl = s->now();
+            for (Live &l : admitted) {
+                const uint64_t tb = l.tile, nb = l.req.n / 16, k = (nb + tb - 1) / tb;
+                const uint32_t nr = s->key_bits[l.req.key] / 32u + 6u;
+                const uint64_t in = reinterpret_cast<uintptr_t>(l.req.in);
+                const uint64_t out = reinterpret_cast<uintptr_t>(s->d_arena + l.req.out_off);
+                for (uint64_t i = 0; i < k; ++i) {
+                    ResTile &r = s->h_ring[l.set][(s->tail[l.set] + i) & (s->ring_cap - 1)];
+                    r.in = in + 16 * i * tb;
+                    r.out = out + 16 * i * tb;
+                    r.n_blocks = uint32_t(std::min<uint64_t>(tb, nb - i * tb));
+                    r.key_slot = l.req.key;
+                    r.nr = nr;
+                    r.req_slot = l.slot;
+                    r.target = s->slot_tiles[l.slot] + uint32_t(k);
+                }
+                s->slot_tiles[l.slot] += uint32_t(k);
+                s->pubs[l.set].push_back(Pub{s->tail[l.set], k, false});
+                l.pub = s->pub_count[l.set]++;
+                s->tail[l.set] += k;
+                l.req.t_launch = tl;
+                live_in_set[l.set]++;
+                s->live[l.slot] = l;
+                s->n_live++;
+            }
+            std::atomic_thread_fence(std::memory_order_release);
+            __atomic_store_n(&s->h_ctl[0], s->tail[0], __ATOMIC_RELEASE);
+            __atomic_store_n(&s->h_ctl[1], s->tail[1], __ATOMIC_RELEASE);
+        }
+        // 4. The kernel: relaunched whenever requests are unfinished and it
+        // has ended (it ends after a while without new tiles).
+        if (s->res_running) {
+            const hipError_t q = hipEventQuery(s->res_event);
+            if (q != hipErrorNotReady) {
+                s->res_running = false;
+                if (q != hipSuccess) {
+                    std::lock_guard<std::mutex> g(s->mu);
+                    s->fatal = AESGPU_EHIP;
+                }
+            }
+        }
+        if (!s->res_running && s->n_live) {
+            const int st = launch_resident_kernel(s);
+            std::lock_guard<std::mutex> g(s->mu);
+            if (st != AESGPU_OK) {
+                // Nothing will complete the requests in flight: fail them.
+                s->fatal = st;
+                const double tf = s->now();
+                std::vector<bool> is_free(kResSlots, false);
+                for (uint32_t f : s->free_slots) is_free[f] = true;
+                for (uint32_t slot = 0; slot < kResSlots; ++slot) {
+                    if (is_free[slot]) continue;
+                    const Live &l = s->live[slot];
+                    aesgpu_done d{};
+                    d.req_id = l.req.id;
+                    d.status = st;
+                    d.d_out = s->d_arena + l.req.out_off;
+                    d.n_bytes = l.req.n;
+                    d.t_arrival = l.req.t_arrival;
+                    d.t_launch = l.req.t_launch;
+                    d.t_done = tf;
+                    s->completed.push_back(d);
+                    s->stats.requests_done++;
+                }
+                s->n_live = 0;
+                return;
+            }
+            s->res_running = true;
+            s->stats.batches++;
+        }
+        // 5. Idle: sleep until a submission or a release; busy: keep polling.
+        if (!s->n_live) {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv.wait_for(lk, std::chrono::milliseconds(2), [&] {
+                return s->stop.load() || s->wake_gen != seen_gen;
+            });
+        } else {
+            std::this_thread::yield();
+        }
+    }
+}
+
 void destroy_server(aesgpu_server *s) {
     if (s->worker.joinable()) {
         s->stop.store(true, std::memory_order_release);
@@ -426,6 +677,19 @@ void destroy_server(aesgpu_server *s) {
         s->worker.join();
     }
     DeviceGuard g(s->ctx->device);
+    if (s->res_stream) {
+        // Ask the resident kernel to end and wait for it (it also ends by
+        // itself after a while without work).
+        if (s->h_ctl) __atomic_store_n(&s->h_ctl[2], uint64_t(1), __ATOMIC_RELEASE);
+        (void)hipStreamSynchronize(s->res_stream);
+        if (s->res_event) (void)hipEventDestroy(s->res_event);
+        (void)hipStreamDestroy(s->res_stream);
+    }
+    for (void *h : {static_cast<void *>(s->h_ring[0]), static_cast<void *>(s->h_ring[1]),
+                    static_cast<void *>(s->h_ctl), static_cast<void *>(s->h_done)})
+        if (h) (void)hipHostFree(h);
+    if (s->d_dev) (void)hipFree(s->d_dev);
+    if (s->d_tiles_done) (void)hipFree(s->d_tiles_done);
     for (Slot &slot : s->slots) {
         if (slot.stream) (void)hipStreamSynchronize(slot.stream);
         if (slot.done) (void)hipEventDestroy(slot.done);
@@ -453,7 +717,7 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
     if (!c.blocks_per_lane) c.blocks_per_lane = 2;
     if (!c.max_queued) c.max_queued = 1u << 20;
     if (!c.direct_requests) c.direct_requests = 4;
-    if (c.n_streams > 8 ||
+    if ((c.flags & ~uint32_t(AESGPU_SERVER_RESIDENT)) || c.n_streams > 8 ||
         (c.blocks_per_lane != 1 && c.blocks_per_lane != 2 && c.blocks_per_lane != 4) ||
         c.tile_blocks % (64u * c.blocks_per_lane) || c.arena_bytes < 256 || c.arena_bytes % 256 ||
         (c.direct_requests > 16 && c.direct_requests != AESGPU_SERVER_NO_DIRECT))
@@ -477,7 +741,8 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
     s->arena.capacity = c.arena_bytes;
     s->arena.granule = 256;
     s->arena.add_free(0, c.arena_bytes);
-    s->slots.resize(c.n_streams);
+    // Resident mode runs on one stream of its own: no batch slots.
+    s->slots.resize((c.flags & AESGPU_SERVER_RESIDENT) ? 0 : c.n_streams);
     s->t0 = Clock::now();
     {
         DeviceGuard g(ctx->device);
@@ -494,13 +759,60 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
             ok = ok && hipMemcpy(slot.d_counters, zeros.data(), kCounterBytes,
                                  hipMemcpyHostToDevice) == hipSuccess;
         }
+        if (ok && (c.flags & AESGPU_SERVER_RESIDENT)) {
+            s->resident = true;
+            s->ring_cap = kResRing;
+            s->n_wg = uint32_t(std::min(std::max(ctx->n_cu, 2), 1024));
+            s->n_wg_forward = s->n_wg / 2;
+            // Fine-grained (coherent) pinned memory: the kernel polls it while
+            // the host writes it, and the reverse.
+            const unsigned fl = hipHostMallocMapped | hipHostMallocCoherent;
+            auto mapped = [&](size_t n, void **h, void **d) {
+                return hipHostMalloc(h, n, fl) == hipSuccess && *h &&
+                       hipHostGetDevicePointer(d, *h, 0) == hipSuccess && *d;
+            };
+            void *h = nullptr, *d = nullptr;
+            for (int set = 0; set < 2 && ok; ++set) {
+                h = d = nullptr;
+                ok = mapped(kResRing * sizeof(ResTile), &h, &d);
+                s->h_ring[set] = static_cast<ResTile *>(h);
+                s->d_ring[set] = static_cast<ResTile *>(d);
+            }
+            h = d = nullptr;
+            ok = ok && mapped(64, &h, &d);
+            s->h_ctl = static_cast<uint64_t *>(h);
+            s->d_ctl = static_cast<uint64_t *>(d);
+            h = d = nullptr;
+            ok = ok && mapped(size_t(kResSlots) * 8, &h, &d);
+            s->h_done = static_cast<uint64_t *>(h);
+            s->d_done = static_cast<uint64_t *>(d);
+            if (ok) {
+                std::memset(s->h_ctl, 0, 64);
+                std::memset(s->h_done, 0, size_t(kResSlots) * 8);
+            }
+            const size_t dev_bytes = res_dev_words(s->n_wg) * 8;
+            const std::vector<uint8_t> zeros(std::max(dev_bytes, size_t(kResSlots) * 4), 0);
+            ok = ok && hipMalloc(&s->d_dev, dev_bytes) == hipSuccess &&
+                 hipMemcpy(s->d_dev, zeros.data(), dev_bytes, hipMemcpyHostToDevice) == hipSuccess;
+            ok = ok && hipMalloc(&s->d_tiles_done, size_t(kResSlots) * 4) == hipSuccess &&
+                 hipMemcpy(s->d_tiles_done, zeros.data(), size_t(kResSlots) * 4,
+                           hipMemcpyHostToDevice) == hipSuccess;
+            ok = ok && hipStreamCreateWithFlags(&s->res_stream, hipStreamNonBlocking) == hipSuccess;
+            ok = ok && hipEventCreateWithFlags(&s->res_event, hipEventDisableTiming) == hipSuccess;
+            if (ok) {
+                s->slot_tiles.assign(kResSlots, 0u);
+                s->live.resize(kResSlots);
+                s->free_slots.reserve(kResSlots);
+                for (uint32_t i = kResSlots; i > 0; --i) s->free_slots.push_back(i - 1);
+            }
+        }
         if (!ok) {
             destroy_server(s);
             return AESGPU_EHIP;
         }
     }
     try {
-        s->worker = std::thread(worker_main, s);
+        s->worker = std::thread(s->resident ? worker_resident : worker_main, s);
     } catch (...) {
         destroy_server(s);
         return AESGPU_ENOMEM;
