@@ -209,7 +209,9 @@ struct aesgpu_server {
     std::vector<Slot> slots;
     std::thread worker;
     std::atomic<bool> stop{false};
-    uint64_t wake_gen = 0;  // bumped by every submission and release (under mu)
+    // Bumped by every submission and release (under mu); read without the
+    // lock by the resident dispatcher to skip admission passes with nothing new.
+    std::atomic<uint64_t> wake_gen{0};
     int fatal = AESGPU_OK;
 
     aesgpu_server_stats stats{};
@@ -409,7 +411,7 @@ void worker_main(aesgpu_server *s) {
             bool backlog = false;
             {
                 std::lock_guard<std::mutex> g(s->mu);
-                seen_gen = s->wake_gen;
+                seen_gen = s->wake_gen.load(std::memory_order_relaxed);
                 uint64_t bytes = 0;
                 while (!s->waiting.empty()) {
                     Req &r = s->waiting.front();
@@ -549,16 +551,21 @@ void worker_resident(aesgpu_server *s) {
             }
         }
         // 2. Admission, in arrival order, while a request slot, ring space
-        // and arena memory are free.
+        // and arena memory are free.  The lock is taken only when there are
+        // completions to hand over, or a submission or release happened (a
+        // pass that stopped for lack of a slot or ring space is retried after
+        // completions, one that stopped for memory after a release): a loop
+        // that takes it every time competes with the callers' submissions and
+        // releases.
         admitted.clear();
-        {
+        if (!finished.empty() || s->wake_gen.load(std::memory_order_acquire) != seen_gen) {
             std::lock_guard<std::mutex> g(s->mu);
             for (const aesgpu_done &d : finished) {
                 s->completed.push_back(d);
                 s->stats.requests_done++;
                 s->stats.bytes_done += d.n_bytes;
             }
-            seen_gen = s->wake_gen;
+            seen_gen = s->wake_gen.load(std::memory_order_relaxed);
             uint64_t planned[2] = {0, 0};  // tiles of requests admitted in this pass
             while (!s->waiting.empty() && !s->free_slots.empty()) {
                 Req &r = s->waiting.front();
@@ -844,7 +851,7 @@ int aesgpu_server_submit(aesgpu_server *s, uint64_t req_id, int dir, uint32_t ke
     if (s->waiting.size() >= s->cfg.max_queued) return AESGPU_EAGAIN;
     s->waiting.push_back(Req{req_id, key_id, uint8_t(dir), d_in, n_bytes, t_arrival, 0, 0.0});
     s->stats.requests_submitted++;
-    s->wake_gen++;
+    s->wake_gen.fetch_add(1, std::memory_order_release);
     s->cv.notify_one();
     return AESGPU_OK;
 }
@@ -868,7 +875,7 @@ int aesgpu_server_release(aesgpu_server *s, const void *d_out, size_t n_bytes) {
     if (p < b || p - b >= s->cfg.arena_bytes) return AESGPU_EINVAL;
     std::lock_guard<std::mutex> g(s->mu);
     if (!s->arena.release(p - b, n_bytes)) return AESGPU_EINVAL;
-    s->wake_gen++;
+    s->wake_gen.fetch_add(1, std::memory_order_release);
     s->cv.notify_one();
     return AESGPU_OK;
 }
@@ -902,15 +909,27 @@ int aesgpu_server_replay(aesgpu_server *s, const aesgpu_request *reqs, size_t n,
         }
         size_t got = 0;
         aesgpu_server_poll(s, buf.data(), buf.size(), &got);
+        int status = AESGPU_OK;
         for (size_t i = 0; i < got; ++i) {
             const aesgpu_done &d = buf[i];
             if (d.req_id >= n || seen[d.req_id]) return AESGPU_EINVAL;
             seen[d.req_id] = 1;
             done[d.req_id] = d;
             ++n_done;
-            if (d.n_bytes) aesgpu_server_release(s, d.d_out, d.n_bytes);
-            if (d.status != AESGPU_OK) return d.status;
+            if (d.status != AESGPU_OK && status == AESGPU_OK) status = d.status;
         }
+        if (got) {
+            // The polled outputs go back to the arena under one lock.
+            std::lock_guard<std::mutex> g(s->mu);
+            const uintptr_t b = reinterpret_cast<uintptr_t>(s->d_arena);
+            for (size_t i = 0; i < got; ++i)
+                if (buf[i].n_bytes)
+                    (void)s->arena.release(reinterpret_cast<uintptr_t>(buf[i].d_out) - b,
+                                           buf[i].n_bytes);
+            s->wake_gen.fetch_add(1, std::memory_order_release);
+            s->cv.notify_one();
+        }
+        if (status != AESGPU_OK) return status;
         if (!got) std::this_thread::yield();
     }
     return AESGPU_OK;
