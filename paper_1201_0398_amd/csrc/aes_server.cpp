@@ -830,15 +830,24 @@ int aesgpu_server_create(aesgpu_ctx *ctx, const uint8_t *keys, const uint16_t *k
 
 double aesgpu_server_now(const aesgpu_server *s) { return s ? s->now() : 0.0; }
 
-int aesgpu_server_submit(aesgpu_server *s, uint64_t req_id, int dir, uint32_t key_id,
-                         const void *d_in, size_t n_bytes, double t_arrival) {
-    if (!s) return AESGPU_EINVAL;
+}  // extern "C"
+
+namespace {
+
+int check_request(const aesgpu_server *s, int dir, uint32_t key_id, const void *d_in,
+                  size_t n_bytes) {
     if (dir != AESGPU_DIR_ENCRYPT && dir != AESGPU_DIR_DECRYPT) return AESGPU_EINVAL;
     if (key_id >= s->n_keys) return AESGPU_EINVAL;
     if (n_bytes % 16 || uint64_t(n_bytes) > s->cfg.arena_bytes) return AESGPU_EINVAL;
     if (n_bytes && !d_in) return AESGPU_EINVAL;
     if (reinterpret_cast<uintptr_t>(d_in) & 15u) return AESGPU_EALIGN;
-    std::lock_guard<std::mutex> g(s->mu);
+    return AESGPU_OK;
+}
+
+// Queues one checked request; the caller holds s->mu and wakes the
+// dispatcher afterwards.
+int enqueue_locked(aesgpu_server *s, uint64_t req_id, int dir, uint32_t key_id,
+                   const void *d_in, size_t n_bytes, double t_arrival) {
     if (s->fatal != AESGPU_OK) return s->fatal;
     if (n_bytes == 0) {
         aesgpu_done d{};
@@ -851,9 +860,25 @@ int aesgpu_server_submit(aesgpu_server *s, uint64_t req_id, int dir, uint32_t ke
     if (s->waiting.size() >= s->cfg.max_queued) return AESGPU_EAGAIN;
     s->waiting.push_back(Req{req_id, key_id, uint8_t(dir), d_in, n_bytes, t_arrival, 0, 0.0});
     s->stats.requests_submitted++;
-    s->wake_gen.fetch_add(1, std::memory_order_release);
-    s->cv.notify_one();
     return AESGPU_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int aesgpu_server_submit(aesgpu_server *s, uint64_t req_id, int dir, uint32_t key_id,
+                         const void *d_in, size_t n_bytes, double t_arrival) {
+    if (!s) return AESGPU_EINVAL;
+    const int c = check_request(s, dir, key_id, d_in, n_bytes);
+    if (c != AESGPU_OK) return c;
+    std::lock_guard<std::mutex> g(s->mu);
+    const int st = enqueue_locked(s, req_id, dir, key_id, d_in, n_bytes, t_arrival);
+    if (st == AESGPU_OK) {
+        s->wake_gen.fetch_add(1, std::memory_order_release);
+        s->cv.notify_one();
+    }
+    return st;
 }
 
 int aesgpu_server_poll(aesgpu_server *s, aesgpu_done *out, size_t cap, size_t *n_out) {
@@ -897,15 +922,30 @@ int aesgpu_server_replay(aesgpu_server *s, const aesgpu_request *reqs, size_t n,
     size_t n_done = 0, next = 0;
     std::vector<aesgpu_done> buf(256);
     while (n_done < n) {
-        // Submit everything whose arrival time has come.
-        while (next < n && s->now() >= t_start + reqs[next].t_arrival) {
-            const aesgpu_request &r = reqs[next];
+        // Submit everything whose arrival time has come, under one lock.
+        const double t_now = s->now();
+        size_t end = next;
+        while (end < n && t_now >= t_start + reqs[end].t_arrival) {
+            const aesgpu_request &r = reqs[end];
             if (r.req_id >= n) return AESGPU_EINVAL;
-            const int st = aesgpu_server_submit(s, r.req_id, r.dir, r.key_id, r.d_in, r.n_bytes,
-                                                t_start + r.t_arrival);
-            if (st == AESGPU_EAGAIN) break;
-            if (st != AESGPU_OK) return st;
-            ++next;
+            const int c = check_request(s, int(r.dir), r.key_id, r.d_in, r.n_bytes);
+            if (c != AESGPU_OK) return c;
+            ++end;
+        }
+        if (end > next) {
+            std::lock_guard<std::mutex> g(s->mu);
+            const size_t first = next;
+            for (; next < end; ++next) {
+                const aesgpu_request &r = reqs[next];
+                const int st = enqueue_locked(s, r.req_id, int(r.dir), r.key_id, r.d_in,
+                                              r.n_bytes, t_start + r.t_arrival);
+                if (st == AESGPU_EAGAIN) break;
+                if (st != AESGPU_OK) return st;
+            }
+            if (next > first) {
+                s->wake_gen.fetch_add(1, std::memory_order_release);
+                s->cv.notify_one();
+            }
         }
         size_t got = 0;
         aesgpu_server_poll(s, buf.data(), buf.size(), &got);
