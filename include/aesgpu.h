@@ -390,6 +390,8 @@ typedef struct {
     uint64_t queued;             /* waiting for admission now */
     uint64_t arena_used;
     uint64_t arena_high_water;
+    uint64_t rebalances;         /* resident mode: kernel stops that changed the split
+                                    of workgroups between encryption and decryption */
 } aesgpu_server_stats;
 
 /*
@@ -411,7 +413,10 @@ typedef struct {
  * rings in pinned host memory, which the dispatcher fills as it admits
  * requests (tiles sized so that a request spreads over the waves that the
  * requests already in flight leave free).  The kernel reports each finished
- * request through a flag in pinned memory.  It ends by itself after tens of
+ * request through a completion ring in pinned memory.  When a large backlog
+ * (a quarter millisecond of the chip or more) leans to one direction by at
+ * least an eighth of the chip, the dispatcher stops the kernel and launches it
+ * with the workgroups split in proportion (between 1/8 and 7/8).  It ends by itself after tens of
  * milliseconds without new tiles and is launched again when requests come;
  * aesgpu_server_destroy() stops it.  While it runs it holds every CU's LDS,
  * so other kernels on the device run only in the registers and waves it

@@ -108,7 +108,8 @@ class aesgpu_host_op(ctypes.Structure):
 class aesgpu_server_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("batches", "requests_submitted", "requests_done", "bytes_done",
-                 "max_batch_requests", "queued", "arena_used", "arena_high_water")]
+                 "max_batch_requests", "queued", "arena_used", "arena_high_water",
+                 "rebalances")]
 
 
 assert ctypes.sizeof(aesgpu_msg) == 48

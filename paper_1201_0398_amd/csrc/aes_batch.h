@@ -113,9 +113,9 @@ constexpr uint32_t kResHostWords = 3;
 
 // Device control block, in 64-bit words, each group on a 128-byte line of its
 // own: the ticket counter of each set at word 16 * set, the count of finished
-// requests at word 32 and the count of waves that have ended at word 40,
-// workgroup w's copy of its set's tail at word 48 + 16 * w and its stop word
-// (the launch epoch that must stop) right after it.  Zero before the first
+// requests at word 32 and the count of waves that have ended at word 40, and
+// from word 48 + 16 * w workgroup w's copies of the tails of ring 0 and ring 1
+// and its stop word (the launch epoch that must stop).  Zero before the first
 // launch.
 constexpr size_t kResDoneWord = 32;
 constexpr size_t kResExitWord = 40;
@@ -135,7 +135,8 @@ struct ResidentLaunch {
     const uint32_t *sched;      // resident schedules (kSchedWords per key slot)
     const uint32_t *tables;
     uint32_t n_wg;              // workgroups (one per CU at most)
-    uint32_t n_wg_forward;      // the first n_wg_forward serve ring 0 (forward tables)
+    uint32_t n_wg_forward;      // the first n_wg_forward serve ring 0 (forward tables);
+                                // may change from one launch to the next
     uint32_t bpl;
     uint32_t epoch;             // launch number, distinguishes stop requests
     uint32_t idle_polls;        // polls without work before the kernel ends

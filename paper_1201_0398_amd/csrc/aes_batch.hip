@@ -633,8 +633,10 @@ __global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
 // tables, ring 1 for the inverse tables) and publishes each ring's tail;
 // workgroups below n_wg_forward serve ring 0, the others ring 1, each with
 // its table set staged once.  Wave 0 of the first workgroup of each set reads
-// the host's tail and stop words over the link and copies the tail to one
-// word per workgroup of its set; the other waves watch their workgroup's copy.
+// the host's tail and stop words over the link and copies its ring's tail into
+// every workgroup's copy block (which holds both rings' tails, so a workgroup
+// that serves the other ring after a relaunch never reads a tail of the
+// wrong ring); the other waves watch their workgroup's copy.
 // A wave takes tiles by tickets: one fetch-and-add on its set's claim counter
 // (a compare-and-swap there serialises thousands of waves), taken only while
 // the copy shows tiles that no ticket covers yet.  A ticket may run ahead of
@@ -694,9 +696,9 @@ __device__ void poll_host(const ResidentLaunch &p, uint32_t set) {
         h = uniform64(h);
         stop = uniform64(stop);
         if (h > seen) {
-            for (uint32_t w = wg0 + lane; w < wg1; w += 64)
-                __hip_atomic_store(p.dev + kResCopyWord + 16 * size_t(w), h, __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
+            for (uint32_t w = lane; w < p.n_wg; w += 64)
+                __hip_atomic_store(p.dev + kResCopyWord + 16 * size_t(w) + set, h,
+                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             seen = h;
             idle = 0;
         }
@@ -704,7 +706,7 @@ __device__ void poll_host(const ResidentLaunch &p, uint32_t set) {
             // Release: a worker that sees the stop word also sees every tail
             // stored before it.
             for (uint32_t w = wg0 + lane; w < wg1; w += 64)
-                __hip_atomic_store(p.dev + kResCopyWord + 16 * size_t(w) + 1,
+                __hip_atomic_store(p.dev + kResCopyWord + 16 * size_t(w) + 2,
                                    uint64_t(p.epoch), __ATOMIC_RELEASE,
                                    __HIP_MEMORY_SCOPE_AGENT);
             return;
@@ -732,15 +734,16 @@ __device__ void serve_ring(const uint32_t *lds, const Bases &b, const ResidentLa
         // thousands of polling waves must not do.
         uint64_t tl = 0, st = 0;
         if (lane == 0) {
-            tl = __hip_atomic_load(copy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            st = __hip_atomic_load(copy + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            tl = __hip_atomic_load(copy + set, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            st = __hip_atomic_load(copy + 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         tl = uniform64(tl);
         st = uniform64(st);
         if (st >= p.epoch) {
             // Stopping: the tail stored before the stop word is visible now.
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (lane == 0) tl = __hip_atomic_load(copy, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (lane == 0)
+                tl = __hip_atomic_load(copy + set, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             tl = uniform64(tl);
             if (ticket == kNoTile || ticket >= tl) break;
         }
@@ -826,8 +829,7 @@ __global__ __launch_bounds__(kWG) void resident_kernel(ResidentLaunch p) {
                                                        __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
         if (before == waves - 1) {
             for (uint32_t set = 0; set < 2; ++set) {
-                const uint32_t wg = set ? p.n_wg_forward : 0u;
-                const uint64_t seen = __hip_atomic_load(p.dev + kResCopyWord + 16 * size_t(wg),
+                const uint64_t seen = __hip_atomic_load(p.dev + kResCopyWord + set,
                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 const uint64_t c = __hip_atomic_load(p.dev + 16 * set, __ATOMIC_RELAXED,
                                                      __HIP_MEMORY_SCOPE_AGENT);

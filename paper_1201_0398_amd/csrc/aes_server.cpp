@@ -230,6 +230,9 @@ struct aesgpu_server {
     hipStream_t res_stream = nullptr;
     hipEvent_t res_event = nullptr;
     bool res_running = false;
+    bool res_restarting = false;                // stop requested to change the split
+    double res_checked = 0;                     // last split check (server clock)
+    uint64_t pending_blocks[2] = {0, 0};        // blocks of unfinished requests per ring
     uint32_t epoch = 0;
     uint32_t n_wg = 0, n_wg_forward = 0;
     uint64_t tail[2] = {0, 0};                  // published tiles per ring
@@ -471,16 +474,35 @@ constexpr uint32_t kResIdlePolls = 25000;          // ≈ tens of ms without wor
 // waves of its set that the requests already in flight leave free (a lone
 // request gets them all), whole steps of the kernel, between 256 blocks
 // and 8192, and never more tiles than half a ring.
-uint64_t resident_tile_blocks(const aesgpu_server *s, uint64_t n_blocks, uint64_t live_in_set) {
+uint64_t resident_tile_blocks(const aesgpu_server *s, uint32_t set, uint64_t n_blocks,
+                              uint64_t live_in_set) {
     if (s->cfg.tile_blocks) return std::max<uint64_t>(s->cfg.tile_blocks,
                                                       (n_blocks + kResRing / 2 - 1) / (kResRing / 2));
     const uint64_t step = 64ull * s->cfg.blocks_per_lane;
-    const uint64_t waves = std::max<uint64_t>(1, uint64_t(s->n_wg / 2) * 16 - 1);
+    const uint64_t wgs = set ? s->n_wg - s->n_wg_forward : s->n_wg_forward;
+    const uint64_t waves = std::max<uint64_t>(1, wgs * 16 - 1);
     const uint64_t share = std::max<uint64_t>(1, waves / (1 + live_in_set));
     uint64_t tb = (n_blocks + share - 1) / share;
     tb = (tb + step - 1) / step * step;
     tb = std::min<uint64_t>(std::max<uint64_t>(tb, std::max<uint64_t>(step, 256)), 8192);
     return std::max<uint64_t>(tb, (n_blocks + kResRing / 2 - 1) / (kResRing / 2));
+}
+
+// Workgroups for ring 0 (forward tables): half, unless the unfinished work
+// is large (≥ kResSplitMin blocks, about a quarter millisecond of the chip)
+// and its mix is at least an eighth of the chip away from the current split;
+// then in proportion to the blocks, between an eighth and seven eighths.
+constexpr uint64_t kResSplitMin = uint64_t(1) << 24;
+constexpr double kResSplitCheck = 2e-3;   // seconds between checks while running
+
+uint32_t resident_split(const aesgpu_server *s) {
+    const uint64_t p0 = s->pending_blocks[0], p1 = s->pending_blocks[1];
+    const uint32_t lo = std::max<uint32_t>(1, s->n_wg / 8), hi = s->n_wg - lo;
+    if (p0 + p1 < kResSplitMin) return s->n_wg_forward;
+    const uint32_t want = uint32_t(std::min<double>(
+        hi, std::max<double>(lo, double(s->n_wg) * double(p0) / double(p0 + p1) + 0.5)));
+    const uint32_t cur = s->n_wg_forward;
+    return (want > cur ? want - cur : cur - want) >= lo ? want : cur;
 }
 
 int launch_resident_kernel(aesgpu_server *s) {
@@ -542,6 +564,7 @@ void worker_resident(aesgpu_server *s) {
             s->pubs[l.set][l.pub - s->pub_base[l.set]].done = true;
             s->free_slots.push_back(l.slot);
             live_in_set[l.set]--;
+            s->pending_blocks[l.set] -= l.req.n / 16;
             s->n_live--;
         }
         for (int set = 0; set < 2; ++set) {
@@ -571,7 +594,8 @@ void worker_resident(aesgpu_server *s) {
                 Req &r = s->waiting.front();
                 const uint32_t set = r.dir == AESGPU_DIR_DECRYPT ? 1u : 0u;
                 const uint64_t nb = r.n / 16;
-                const uint64_t tb = resident_tile_blocks(s, nb, live_in_set[set] + admitted.size());
+                const uint64_t tb =
+                    resident_tile_blocks(s, set, nb, live_in_set[set] + admitted.size());
                 const uint64_t k = (nb + tb - 1) / tb;
                 const uint64_t head = s->pubs[set].empty() ? s->tail[set] : s->pubs[set].front().first;
                 if (s->tail[set] + planned[set] + k - head > s->ring_cap) break;
@@ -617,6 +641,7 @@ void worker_resident(aesgpu_server *s) {
                 s->tail[l.set] += k;
                 l.req.t_launch = tl;
                 live_in_set[l.set]++;
+                s->pending_blocks[l.set] += nb;
                 s->live[l.slot] = l;
                 s->n_live++;
             }
@@ -625,18 +650,33 @@ void worker_resident(aesgpu_server *s) {
             __atomic_store_n(&s->h_ctl[1], s->tail[1], __ATOMIC_RELEASE);
         }
         // 4. The kernel: relaunched whenever requests are unfinished and it
-        // has ended (it ends after a while without new tiles).
+        // has ended (it ends after a while without new tiles).  While it
+        // runs, a backlog whose direction mix is far from the workgroups'
+        // split stops it, and the next launch splits them anew.
         if (s->res_running) {
             const hipError_t q = hipEventQuery(s->res_event);
             if (q != hipErrorNotReady) {
                 s->res_running = false;
+                if (s->res_restarting) {
+                    __atomic_store_n(&s->h_ctl[2], uint64_t(0), __ATOMIC_RELEASE);
+                    s->res_restarting = false;
+                }
                 if (q != hipSuccess) {
                     std::lock_guard<std::mutex> g(s->mu);
                     s->fatal = AESGPU_EHIP;
                 }
+            } else if (!s->res_restarting && t - s->res_checked > kResSplitCheck) {
+                s->res_checked = t;
+                if (resident_split(s) != s->n_wg_forward) {
+                    __atomic_store_n(&s->h_ctl[2], uint64_t(1), __ATOMIC_RELEASE);
+                    s->res_restarting = true;
+                    std::lock_guard<std::mutex> g(s->mu);
+                    s->stats.rebalances++;
+                }
             }
         }
         if (!s->res_running && s->n_live) {
+            s->n_wg_forward = resident_split(s);
             const int st = launch_resident_kernel(s);
             std::lock_guard<std::mutex> g(s->mu);
             if (st != AESGPU_OK) {

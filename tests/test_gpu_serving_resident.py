@@ -179,6 +179,49 @@ def test_resident_kernel_ends_when_idle_and_restarts(A, ctx, pool):
         A.aesgpu_server_destroy(server)
 
 
+def test_resident_rebalances_one_direction_backlog(A, ctx, pool):
+    """A large one-direction backlog makes the server stop the kernel and
+    launch it with more workgroups on that direction's tables; every output
+    is still exact (sampled against the oracle, then round-tripped through a
+    decryption backlog, which moves the split back)."""
+    import torch
+    tr = pool
+    n = 16 << 20
+    m = 48                      # 48 x 16 MiB = 48 M blocks of one direction
+    rng = np.random.default_rng(91)
+    data = rng.integers(0, 256, n, dtype=np.uint8)
+    src = torch.from_numpy(data).to("cuda")
+    server = _server(A, ctx, tr, arena_bytes=2 << 30)
+    try:
+        log("case: resident, encryption-only backlog behind a kernel split half and half")
+        outs = {}
+        # A small request starts the kernel at the even split; the backlog
+        # comes while it runs (it stays up for tens of milliseconds idle).
+        A.aesgpu_server_submit(server, 10_000, 1, 3, src.data_ptr(), 1 << 16)
+        _drain(A, server, 1, {})
+        time.sleep(0.005)
+        for j in range(m):
+            A.aesgpu_server_submit(server, j, 0, j % 64, src.data_ptr(), n)
+        _drain(A, server, m, outs)
+        st = A.aesgpu_server_get_stats(server)
+        log(f"launches {st.batches}, rebalances {st.rebalances}")
+        assert st.rebalances >= 1 and st.batches >= 2, "the split did not change"
+        idx = np.unique(np.concatenate([np.arange(1024), rng.integers(0, n // 16, 2048)]))
+        for j in (0, 1, m - 1):
+            key = tr.pool_keys[j % 64, : tr.pool_bits[j % 64] // 8]
+            assert np.array_equal(outs[j].reshape(-1, 16)[idx], oracle.ecb_sampled(key, data, idx))
+        log("case: resident, decryption-only backlog of the ciphertexts")
+        cts = [torch.from_numpy(outs[j]).to("cuda") for j in range(m)]
+        back = {}
+        for j in range(m):
+            A.aesgpu_server_submit(server, m + j, 1, j % 64, cts[j].data_ptr(), n)
+        _drain(A, server, m, back)
+        for j in range(m):
+            assert np.array_equal(back[m + j], data), f"request {j}: decrypt(encrypt(x)) != x"
+    finally:
+        A.aesgpu_server_destroy(server)
+
+
 def test_resident_replay_poisson_trace(A, ctx):
     import torch
     from paper_1201_0398_amd import workloads
