@@ -646,13 +646,17 @@ __global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
 // carries the count that completes its request) appends the slot to a
 // completion ring in host memory, each entry tagged with its position so
 // that the host reads the ring in order.
+// Tiles load and store with the agent-coherent cache policy, so a tile sees
+// its input and publishes its output device-wide with no per-tile fence (an
+// L2 invalidation or write-back at this scope, which would serialise).
 // Every wave ends: the poller after the host's stop word or idle_polls polls
 // without a new tail (it then posts the launch epoch in every stop word of its
 // set), a worker once its set's stop word holds the epoch (after serving a
 // ticket that is published by then), or after 4 * idle_polls idle polls of
-// its own (64 * idle_polls while it holds a ticket).  The last wave to end points each claim
-// counter back at the first tile that no wave served (tickets that ran ahead
-// and were never published), so the next launch starts there.
+// its own (64 * idle_polls while it holds a ticket).  The last wave to end
+// points each claim counter back at the first tile that no wave served
+// (tickets that ran ahead and were never published), so the next launch
+// starts there.
 
 constexpr uint64_t kNoTile = ~0ull;
 
@@ -677,7 +681,8 @@ __device__ __forceinline__ ResTile load_record(const ResTile *r) {
     return t;
 }
 
-// The set's poller: the host tail and stop words, copied to the set's
+// The set's poller: its ring's host tail, copied to every workgroup, and the
+// host's stop word, passed on as this launch's epoch to its set's
 // workgroups.
 __device__ void poll_host(const ResidentLaunch &p, uint32_t set) {
     const uint32_t lane = threadIdx.x & 63u;

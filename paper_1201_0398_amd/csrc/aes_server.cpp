@@ -488,17 +488,18 @@ uint64_t resident_tile_blocks(const aesgpu_server *s, uint32_t set, uint64_t n_b
     return std::max<uint64_t>(tb, (n_blocks + kResRing / 2 - 1) / (kResRing / 2));
 }
 
-// Workgroups for ring 0 (forward tables): half, unless the unfinished work
-// is large (≥ kResSplitMin blocks, about a quarter millisecond of the chip)
-// and its mix is at least an eighth of the chip away from the current split;
-// then in proportion to the blocks, between an eighth and seven eighths.
+// Workgroups for ring 0 (forward tables).  When the unfinished work is large
+// (≥ kResSplitMin blocks, about a quarter millisecond of the chip) and its mix
+// is at least an eighth of the chip away from the current split: in
+// proportion to the blocks, between an eighth and seven eighths.  Otherwise
+// the current split while the kernel runs, and half at a launch.
 constexpr uint64_t kResSplitMin = uint64_t(1) << 24;
 constexpr double kResSplitCheck = 2e-3;   // seconds between checks while running
 
-uint32_t resident_split(const aesgpu_server *s) {
+uint32_t resident_split(const aesgpu_server *s, bool at_launch) {
     const uint64_t p0 = s->pending_blocks[0], p1 = s->pending_blocks[1];
     const uint32_t lo = std::max<uint32_t>(1, s->n_wg / 8), hi = s->n_wg - lo;
-    if (p0 + p1 < kResSplitMin) return s->n_wg_forward;
+    if (p0 + p1 < kResSplitMin) return at_launch ? s->n_wg / 2 : s->n_wg_forward;
     const uint32_t want = uint32_t(std::min<double>(
         hi, std::max<double>(lo, double(s->n_wg) * double(p0) / double(p0 + p1) + 0.5)));
     const uint32_t cur = s->n_wg_forward;
@@ -667,7 +668,7 @@ void worker_resident(aesgpu_server *s) {
                 }
             } else if (!s->res_restarting && t - s->res_checked > kResSplitCheck) {
                 s->res_checked = t;
-                if (resident_split(s) != s->n_wg_forward) {
+                if (resident_split(s, false) != s->n_wg_forward) {
                     __atomic_store_n(&s->h_ctl[2], uint64_t(1), __ATOMIC_RELEASE);
                     s->res_restarting = true;
                     std::lock_guard<std::mutex> g(s->mu);
@@ -676,7 +677,7 @@ void worker_resident(aesgpu_server *s) {
             }
         }
         if (!s->res_running && s->n_live) {
-            s->n_wg_forward = resident_split(s);
+            s->n_wg_forward = resident_split(s, true);
             const int st = launch_resident_kernel(s);
             std::lock_guard<std::mutex> g(s->mu);
             if (st != AESGPU_OK) {
