@@ -222,6 +222,37 @@ def test_resident_rebalances_one_direction_backlog(A, ctx, pool):
         A.aesgpu_server_destroy(server)
 
 
+def test_resident_destroy_with_work_in_flight(A, ctx, pool):
+    """Destroying the server while requests are queued and running stops the
+    kernel (queued tiles are dropped) and returns promptly; a new server on
+    the same context then works."""
+    import torch
+    tr = pool
+    n = 16 << 20
+    src = torch.zeros(n, dtype=torch.uint8, device="cuda")
+    server = _server(A, ctx, tr, arena_bytes=2 << 30)
+    for j in range(100):
+        A.aesgpu_server_submit(server, j, j % 2, j % 64, src.data_ptr(), n)
+    time.sleep(0.002)
+    t0 = time.time()
+    A.aesgpu_server_destroy(server)
+    log(f"destroy with work in flight took {(time.time() - t0) * 1e3:.1f} ms")
+    assert time.time() - t0 < 5.0
+    torch.cuda.synchronize()
+    server = _server(A, ctx, tr, arena_bytes=16 << 20)
+    try:
+        outs = {}
+        base = torch.from_numpy(tr.source.copy()).to("cuda")
+        for j in range(10):
+            A.aesgpu_server_submit(server, j, int(tr.dirs[j]), int(tr.key_ids[j]),
+                                   base.data_ptr() + int(tr.src_offsets[j]), int(tr.sizes[j]))
+        _drain(A, server, 10, outs)
+        for j in range(10):
+            assert np.array_equal(outs[j], _expected(tr, j)), f"request {j}"
+    finally:
+        A.aesgpu_server_destroy(server)
+
+
 def test_resident_replay_poisson_trace(A, ctx):
     import torch
     from paper_1201_0398_amd import workloads
