@@ -534,7 +534,7 @@ def main() -> int:
                          "reads_per_block": LDS_READS_PER_BLOCK[dominant]},
         "kernels": per_kernel,
     }
-    # The achievable HBM ceiling on this machine: a plain device copy of the same
+    # The achievable HBM ceiling on this GPU: a plain device copy of the same
     # size (torch's copy kernel), read + write bytes over its event time.
     copy = lambda: d_pt.copy_(d_in)  # noqa: E731
     warm_up(torch, copy, 0.1)
