@@ -2,8 +2,10 @@
 takes tiles from rings in pinned host memory): every request's output equals
 the oracle's, a request alone gives the same bytes as in the mix, a tiny
 arena and a large request spread over many tiles keep outputs exact, the
-kernel ends by itself when idle and is launched again for new requests, and
-the trace replay reports consistent timestamps."""
+kernel ends by itself when idle and is launched again for new requests, a
+one-direction backlog moves the split of workgroups between the table sets,
+destroying the server with work in flight returns promptly, and the trace
+replay reports consistent timestamps."""
 import time
 
 import numpy as np
