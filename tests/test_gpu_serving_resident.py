@@ -97,13 +97,16 @@ def test_resident_mix_and_alone_match_oracle(A, ctx, pool):
         A.aesgpu_server_destroy(server)
 
 
-def test_resident_tiny_arena(A, ctx, pool):
+@pytest.mark.parametrize("bpl", [1, 2, 4])
+def test_resident_tiny_arena(A, ctx, pool, bpl):
+    """A 128 KiB arena forces slot and memory reuse; every blocks-per-lane
+    variant of the kernel."""
     import torch
     tr = pool
     src = torch.from_numpy(tr.source.copy()).to("cuda")
     base = src.data_ptr()
-    log("case: resident, 128 KiB arena")
-    server = _server(A, ctx, tr, arena_bytes=1 << 17)
+    log(f"case: resident, 128 KiB arena, {bpl} blocks per lane")
+    server = _server(A, ctx, tr, arena_bytes=1 << 17, blocks_per_lane=bpl)
     try:
         outs = {}
         n = 300
