@@ -108,3 +108,34 @@ def test_strerror_names_every_code(A):
     for st in range(-7, 1):
         assert A.aesgpu_strerror(st) and A.aesgpu_strerror(st) != "unknown status"
     assert A.aesgpu_strerror(-99) == "unknown status"
+
+
+STRUCTS = ["aesgpu_key", "aesgpu_msg", "aesgpu_batch_config", "aesgpu_batch_stats",
+           "aesgpu_server_config", "aesgpu_done", "aesgpu_request", "aesgpu_host_op",
+           "aesgpu_server_stats"]
+
+
+def test_binding_structs_match_the_header(A, tmp_path):
+    """Every ctypes mirror has the C struct's size and each field's offset,
+    as a C compiler lays them out from include/aesgpu.h."""
+    lines = ["#include <stdio.h>", "#include <stddef.h>", '#include "aesgpu.h"', "int main(void) {"]
+    for name in STRUCTS:
+        cls = getattr(A, name)
+        lines.append(f'  printf("{name} sizeof %zu\\n", sizeof({name}));')
+        for field, _ in cls._fields_:
+            lines.append(f'  printf("{name} {field} %zu\\n", offsetof({name}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c11", "-I", HEADER_DIR, str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout
+    c_layout = {}
+    for line in out.splitlines():
+        name, field, value = line.split()
+        c_layout[(name, field)] = int(value)
+    for name in STRUCTS:
+        cls = getattr(A, name)
+        assert ctypes.sizeof(cls) == c_layout[(name, "sizeof")], name
+        for field, _ in cls._fields_:
+            assert getattr(cls, field).offset == c_layout[(name, field)], f"{name}.{field}"
