@@ -649,14 +649,22 @@ __global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
 // Tiles load and store with the agent-coherent cache policy, so a tile sees
 // its input and publishes its output device-wide with no per-tile fence (an
 // L2 invalidation or write-back at this scope, which would serialise).
-// Every wave ends: the poller after the host's stop word or idle_polls polls
-// without a new tail (it then posts the launch epoch in every stop word of its
-// set), a worker once its set's stop word holds the epoch (after serving a
-// ticket that is published by then), or after 4 * idle_polls idle polls of
-// its own (64 * idle_polls while it holds a ticket).  The last wave to end
-// points each claim counter back at the first tile that no wave served
-// (tickets that ran ahead and were never published), so the next launch
-// starts there.
+// Tickets ahead of the tail are bounded: a wave takes one only while the
+// claim counter is less than the tail plus twice its set's workgroups, so a
+// new tail at low load does not send every idle wave of the set to wait on a
+// tile of its own.
+// Every wave ends, and only on its set's stop word: the poller ends after the
+// host's stop word or idle_polls polls without a new tail and then posts the
+// launch epoch in every stop word of its set; a worker ends once that word
+// holds the epoch (after serving a ticket that is published by then).  A
+// worker never leaves on a timer of its own: a ticket it gave up would be
+// below a later tail and never served, and a set whose workers had left
+// would leave its poller publishing tiles that nobody takes.  (Workgroups
+// are dispatched in order of their index, so each set's poller, in the
+// set's first workgroup, is resident before any of its workers.)  The last
+// wave to end points each claim counter back at the first tile that no wave
+// served (tickets that ran ahead and were never published), so the next
+// launch starts there.
 
 constexpr uint64_t kNoTile = ~0ull;
 
@@ -733,7 +741,7 @@ __device__ void serve_ring(const uint32_t *lds, const Bases &b, const ResidentLa
     bp.tables = p.tables;
     uint64_t known = 0;         // tickets reached this tail when last taken
     uint64_t ticket = kNoTile;  // this wave's tile, perhaps not yet published
-    uint32_t idle = 0;
+    const uint64_t ahead = 2ull * (kInv ? p.n_wg - p.n_wg_forward : p.n_wg_forward);
     for (;;) {
         // Relaxed polls: an acquire at this scope invalidates the L2, which
         // thousands of polling waves must not do.
@@ -753,15 +761,20 @@ __device__ void serve_ring(const uint32_t *lds, const Bases &b, const ResidentLa
             if (ticket == kNoTile || ticket >= tl) break;
         }
         if (ticket == kNoTile && tl > known) {
-            uint64_t t = 0;
-            if (lane == 0)
-                t = __hip_atomic_fetch_add(claimed, 1ull, __ATOMIC_RELAXED,
-                                           __HIP_MEMORY_SCOPE_AGENT);
+            uint64_t t = kNoTile;
+            if (lane == 0) {
+                const uint64_t c = __hip_atomic_load(claimed, __ATOMIC_RELAXED,
+                                                     __HIP_MEMORY_SCOPE_AGENT);
+                if (c < tl + ahead)
+                    t = __hip_atomic_fetch_add(claimed, 1ull, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_AGENT);
+            }
             ticket = uniform64(t);
-            if (ticket >= tl) known = tl;  // every published tile has a ticket
+            // No ticket, or one at or past the tail: every published tile
+            // has a ticket.
+            if (ticket == kNoTile || ticket >= tl) known = tl;
         }
         if (ticket != kNoTile && ticket < tl) {
-            idle = 0;
             const ResTile r = load_record(p.ring[set] + (ticket & p.ring_mask));
             ticket = kNoTile;
             DevMsg m{};
@@ -797,12 +810,8 @@ __device__ void serve_ring(const uint32_t *lds, const Bases &b, const ResidentLa
             }
             continue;
         }
-        // A wave holding a ticket waits for its tile until the stop word; one
-        // without a ticket also ends after a long idle spell, and one with a
-        // ticket after a much longer one (a ticket given up that way is
-        // served after the next launch: the last wave out rewinds the
-        // counter to it).
-        if (++idle > (ticket == kNoTile ? 4u : 64u) * p.idle_polls) break;
+        // Nothing to run: wait for a new tail or the stop word (a wave
+        // holding a ticket polls more often, its tile comes next).
         if (ticket == kNoTile)
             __builtin_amdgcn_s_sleep(32);
         else

@@ -280,3 +280,61 @@ def test_resident_replay_poisson_trace(A, ctx):
         assert A.aesgpu_server_get_stats(server).arena_used == 0
     finally:
         A.aesgpu_server_destroy(server)
+
+
+def test_resident_steady_trickle_every_request_completes(A, ctx, pool):
+    """Light steady traffic: one 4 KiB request every 2..5 ms for about three
+    seconds, so the kernel stays up (each new tail restarts its idle count)
+    while most of its waves have nothing to do for seconds.  Every request
+    must finish within a deadline and equal the oracle's output (a wave that
+    left on a timer of its own while holding a ticket, or every worker of a
+    set leaving while the set's poller still ran, would strand a request)."""
+    import torch
+    tr = pool
+    src = torch.from_numpy(tr.source.copy()).to("cuda")
+    base = src.data_ptr()
+    rng = np.random.default_rng(123)
+    n = 800
+    dirs = rng.integers(0, 2, n)
+    keys = rng.integers(0, 64, n)
+    offs = 16 * rng.integers(0, (tr.source.size - 4096) // 16, n)
+    gaps = rng.uniform(0.002, 0.005, n)
+    server = _server(A, ctx, tr, arena_bytes=16 << 20)
+    log(f"case: resident, trickle of {n} 4 KiB requests, 2..5 ms apart")
+    try:
+        outs, t_sub, t_got = {}, {}, {}
+        j = 0
+        next_t = time.time()
+        deadline = time.time() + gaps.sum() + 30.0
+        while len(outs) < n:
+            now = time.time()
+            assert now < deadline, f"{n - len(outs)} requests never finished"
+            if j < n and now >= next_t:
+                A.aesgpu_server_submit(server, j, int(dirs[j]), int(keys[j]), base + int(offs[j]),
+                                       4096)
+                t_sub[j] = time.time()
+                next_t = t_sub[j] + gaps[j]
+                j += 1
+            for d in A.aesgpu_server_poll(server):
+                assert d.status == 0, f"request {d.req_id} failed: {d.status}"
+                out = torch.empty(d.n_bytes, dtype=torch.uint8, device="cuda")
+                copy_device(out.data_ptr(), d.d_out, d.n_bytes)
+                outs[d.req_id] = from_dev(out)
+                t_got[d.req_id] = time.time()
+                A.aesgpu_server_release(server, d.d_out, d.n_bytes)
+            pending = [q for q in range(max(0, j - 64), j) if q not in t_got]
+            if pending:
+                q = pending[0]
+                assert time.time() - t_sub[q] < 2.0, f"request {q} stranded"
+            time.sleep(0.0002)
+        lat = np.array([t_got[q] - t_sub[q] for q in range(n)])
+        st = A.aesgpu_server_get_stats(server)
+        log(f"trickle: kernel launches {st.batches}, latency p50 {np.median(lat) * 1e3:.2f} ms, "
+            f"max {lat.max() * 1e3:.2f} ms")
+        for q in range(n):
+            k = int(keys[q])
+            key = tr.pool_keys[k, : tr.pool_bits[k] // 8]
+            want = oracle.ecb(key, tr.source[offs[q]: offs[q] + 4096], decrypt=bool(dirs[q]))
+            assert np.array_equal(outs[q], want), f"request {q}"
+    finally:
+        A.aesgpu_server_destroy(server)
