@@ -50,7 +50,9 @@ enum {
     AESGPU_ECTR_OVERFLOW = -4, /* 32-bit block counter would wrap */
     AESGPU_ENOMEM = -5,        /* device or host allocation failed */
     AESGPU_EHIP = -6,          /* a HIP runtime call or launch failed */
-    AESGPU_EAGAIN = -7         /* server full: retry after polling */
+    AESGPU_EAGAIN = -7,        /* server full: retry after polling */
+    AESGPU_ESCRATCH = -8       /* batch larger than the fixed scratch of
+                                  aesgpu_batch_run_noalloc() */
 };
 
 typedef struct aesgpu_ctx aesgpu_ctx;
@@ -232,6 +234,30 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
 int aesgpu_batch_run(aesgpu_batch *plan, const uint8_t *d_keys, size_t n_key_slots,
                      const void *d_in, size_t in_bytes, void *d_out, size_t out_bytes,
                      aesgpu_stream_t stream);
+
+/*
+ * For callers that cannot allocate device memory (tight serving loops,
+ * harnesses that forbid hipMalloc): plans and runs one batch in a single call
+ * and allocates no device memory.  Messages, keys, buffers, stream and cfg
+ * mean what they mean for aesgpu_batch_plan() and aesgpu_batch_run(), with the
+ * same errors; the launches are enqueued directly (no hipGraph).  The batch's
+ * device descriptors (64 bytes per message, 16 per tile, the queue counters
+ * and the CBC-encryption groups) go to a fixed scratch area of
+ * AESGPU_NOALLOC_SCRATCH_BYTES that each GPU the library runs on holds until
+ * the process ends; a batch needing more returns AESGPU_ESCRATCH before any
+ * HIP call (65,536 messages of up to 1 MiB in 8192-block tiles need about
+ * 6 MB).  The descriptors are built on the host and copied on `stream` from
+ * pageable host memory (a copy that completes before the call returns).
+ * Every call on one GPU uses that GPU's one scratch area: calls whose runs
+ * overlap in time on one GPU (other streams, other contexts, other threads)
+ * race and give undefined output; serialise them, for instance on one
+ * stream.  Errors: EINVAL, EKEYLEN, EALIGN, ECTR_OVERFLOW, ESCRATCH, EHIP.
+ */
+#define AESGPU_NOALLOC_SCRATCH_BYTES (8u << 20)
+int aesgpu_batch_run_noalloc(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
+                             const aesgpu_batch_config *cfg, const uint8_t *d_keys,
+                             size_t n_key_slots, const void *d_in, size_t in_bytes, void *d_out,
+                             size_t out_bytes, aesgpu_stream_t stream);
 
 /* Plan statistics (host only).  Errors: EINVAL. */
 int aesgpu_batch_info(const aesgpu_batch *plan, aesgpu_batch_stats *out);

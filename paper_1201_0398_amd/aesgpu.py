@@ -28,6 +28,8 @@ AESGPU_ECTR_OVERFLOW = -4
 AESGPU_ENOMEM = -5
 AESGPU_EHIP = -6
 AESGPU_EAGAIN = -7
+AESGPU_ESCRATCH = -8
+AESGPU_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class AesgpuError(RuntimeError):
@@ -137,6 +139,9 @@ def _load() -> ctypes.CDLL:
         "aesgpu_batch_plan": ([vp, ctypes.POINTER(aesgpu_msg), sz,
                                ctypes.POINTER(aesgpu_batch_config), ctypes.POINTER(vp)], ci),
         "aesgpu_batch_run": ([vp, vp, sz, vp, sz, vp, sz, vp], ci),
+        "aesgpu_batch_run_noalloc": ([vp, ctypes.POINTER(aesgpu_msg), sz,
+                                      ctypes.POINTER(aesgpu_batch_config), vp, sz, vp, sz, vp,
+                                      sz, vp], ci),
         "aesgpu_batch_info": ([vp, ctypes.POINTER(aesgpu_batch_stats)], ci),
         "aesgpu_batch_free": ([vp], None),
         "aesgpu_arena_create": ([ctypes.c_uint64, ctypes.c_uint64, ctypes.POINTER(vp)], ci),
@@ -360,6 +365,24 @@ def aesgpu_batch_run(plan, d_keys, n_key_slots: int, d_in, d_out, in_bytes: int 
                                _ptr(d_in, in_bytes), in_bytes, _ptr(d_out, out_bytes),
                                out_bytes, _stream(stream))
     return _check(st, "aesgpu_batch_run") if check else st
+
+
+def aesgpu_batch_run_noalloc(ctx, msgs, d_keys, n_key_slots: int, d_in, d_out,
+                             in_bytes: int | None = None, out_bytes: int | None = None,
+                             blocks_per_lane: int = 0, tile_blocks: int = 0, stream=None,
+                             check: bool = True) -> int:
+    """Plans and runs one batch with no device allocation (the library's
+    fixed per-GPU scratch holds the descriptors)."""
+    if in_bytes is None:
+        in_bytes = _nbytes(d_in)
+    if out_bytes is None:
+        out_bytes = _nbytes(d_out)
+    cfg = aesgpu_batch_config(blocks_per_lane, tile_blocks, 0)
+    st = _lib.aesgpu_batch_run_noalloc(ctx, msgs, len(msgs), ctypes.byref(cfg),
+                                       _ptr(d_keys, 32 * n_key_slots), n_key_slots,
+                                       _ptr(d_in, in_bytes), in_bytes, _ptr(d_out, out_bytes),
+                                       out_bytes, _stream(stream))
+    return _check(st, "aesgpu_batch_run_noalloc") if check else st
 
 
 def aesgpu_batch_info(plan) -> aesgpu_batch_stats:

@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -1021,6 +1022,35 @@ constexpr uint32_t kDefaultBpl = 4;
 constexpr uint32_t kDefaultTileBlocks = 8192;
 }  // namespace
 
+// Descriptor scratch of aesgpu_batch_run_noalloc(): one copy on each GPU the
+// library runs on, held until the process ends.  In host code this name is a
+// host-side stand-in, not a device address: host code uses only the address
+// hipGetSymbolAddress returns for the current device (scratch_address()).
+static __device__ __align__(256) uint8_t scratch[AESGPU_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+// The device address of this GPU's scratch, looked up once per device with
+// that device current (each GPU holds its own copy at its own address).
+void *scratch_address(int device) {
+    if (device < 0 || device >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return nullptr;
+        g_scratch_ptr[device] = p;
+    }
+    return g_scratch_ptr[device];
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
 struct aesgpu_batch {
     aesgpu_ctx *ctx = nullptr;
     uint32_t bpl = kDefaultBpl;
@@ -1045,6 +1075,38 @@ struct aesgpu_batch {
 };
 
 namespace {
+
+// Checks of a run's buffers against a planned batch's totals (every
+// message inside d_in / d_out, key slots present, no partial overlap).
+int check_run(const BatchTotals &tot, const uint8_t *d_keys, size_t n_key_slots,
+              const void *d_in, size_t in_bytes, const void *d_out, size_t out_bytes) {
+    if (!d_keys || !d_in || !d_out) return AESGPU_EINVAL;
+    if ((reinterpret_cast<uintptr_t>(d_keys) | reinterpret_cast<uintptr_t>(d_in) |
+         reinterpret_cast<uintptr_t>(d_out)) & 15u)
+        return AESGPU_EALIGN;
+    if (uint64_t(tot.max_slot) >= n_key_slots) return AESGPU_EINVAL;
+    if (tot.in_end > in_bytes || tot.out_end > out_bytes) return AESGPU_EINVAL;
+    const uintptr_t i0 = reinterpret_cast<uintptr_t>(d_in), o0 = reinterpret_cast<uintptr_t>(d_out);
+    if (i0 != o0 && i0 < o0 + out_bytes && o0 < i0 + in_bytes) return AESGPU_EINVAL;
+    if (i0 == o0 && tot.cbc_dec_self_overlap) return AESGPU_EINVAL;
+    return AESGPU_OK;
+}
+
+// The launch shape a config asks for (NULL: the defaults).
+int batch_shape(const aesgpu_batch_config *cfg, uint32_t &bpl, uint32_t &tile_blocks,
+                bool &use_graph) {
+    bpl = kDefaultBpl;
+    tile_blocks = kDefaultTileBlocks;
+    use_graph = true;
+    if (cfg) {
+        if (cfg->blocks_per_lane) bpl = cfg->blocks_per_lane;
+        if (cfg->tile_blocks) tile_blocks = cfg->tile_blocks;
+        use_graph = !(cfg->flags & AESGPU_BATCH_NO_GRAPH);
+    }
+    if (bpl != 1 && bpl != 2 && bpl != 4) return AESGPU_EINVAL;
+    if (tile_blocks % (64u * bpl) != 0 || tile_blocks > (1u << 24)) return AESGPU_EINVAL;
+    return AESGPU_OK;
+}
 
 void release_graph(aesgpu_batch *b) {
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
@@ -1087,15 +1149,10 @@ int aesgpu_batch_plan(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     *out = nullptr;
     if (!ctx || (m > 0 && !msgs)) return AESGPU_EINVAL;
     if (m > 0xFFFFFFFFull) return AESGPU_EINVAL;
-    uint32_t bpl = kDefaultBpl, tile_blocks = kDefaultTileBlocks;
-    bool use_graph = true;
-    if (cfg) {
-        if (cfg->blocks_per_lane) bpl = cfg->blocks_per_lane;
-        if (cfg->tile_blocks) tile_blocks = cfg->tile_blocks;
-        use_graph = !(cfg->flags & AESGPU_BATCH_NO_GRAPH);
-    }
-    if (bpl != 1 && bpl != 2 && bpl != 4) return AESGPU_EINVAL;
-    if (tile_blocks % (64u * bpl) != 0 || tile_blocks > (1u << 24)) return AESGPU_EINVAL;
+    uint32_t bpl, tile_blocks;
+    bool use_graph;
+    const int shape = batch_shape(cfg, bpl, tile_blocks, use_graph);
+    if (shape != AESGPU_OK) return shape;
 
     std::vector<DevMsg> dm;
     std::vector<Tile> tiles[2];
@@ -1171,15 +1228,8 @@ int aesgpu_batch_run(aesgpu_batch *b, const uint8_t *d_keys, size_t n_key_slots,
                      size_t in_bytes, void *d_out, size_t out_bytes, aesgpu_stream_t stream) {
     if (!b) return AESGPU_EINVAL;
     if (b->n_tiles[0] + b->n_tiles[1] + b->n_cbc_groups == 0) return AESGPU_OK;
-    if (!d_keys || !d_in || !d_out) return AESGPU_EINVAL;
-    if ((reinterpret_cast<uintptr_t>(d_keys) | reinterpret_cast<uintptr_t>(d_in) |
-         reinterpret_cast<uintptr_t>(d_out)) & 15u)
-        return AESGPU_EALIGN;
-    if (uint64_t(b->tot.max_slot) >= n_key_slots) return AESGPU_EINVAL;
-    if (b->tot.in_end > in_bytes || b->tot.out_end > out_bytes) return AESGPU_EINVAL;
-    const uintptr_t i0 = reinterpret_cast<uintptr_t>(d_in), o0 = reinterpret_cast<uintptr_t>(d_out);
-    if (i0 != o0 && i0 < o0 + out_bytes && o0 < i0 + in_bytes) return AESGPU_EINVAL;
-    if (i0 == o0 && b->tot.cbc_dec_self_overlap) return AESGPU_EINVAL;
+    const int chk = check_run(b->tot, d_keys, n_key_slots, d_in, in_bytes, d_out, out_bytes);
+    if (chk != AESGPU_OK) return chk;
     DeviceGuard g(b->ctx->device);
     if (!g.ok()) return AESGPU_EHIP;
     hipStream_t s = reinterpret_cast<hipStream_t>(stream);
@@ -1230,6 +1280,81 @@ void aesgpu_batch_free(aesgpu_batch *b) {
         if (b->d_mem) (void)hipFree(b->d_mem);
     }
     delete b;
+}
+
+int aesgpu_batch_run_noalloc(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
+                             const aesgpu_batch_config *cfg, const uint8_t *d_keys,
+                             size_t n_key_slots, const void *d_in, size_t in_bytes, void *d_out,
+                             size_t out_bytes, aesgpu_stream_t stream) {
+    if (!ctx || (m > 0 && !msgs)) return AESGPU_EINVAL;
+    if (m > 0xFFFFFFFFull) return AESGPU_EINVAL;
+    uint32_t bpl, tile_blocks;
+    bool use_graph;
+    const int shape = batch_shape(cfg, bpl, tile_blocks, use_graph);
+    if (shape != AESGPU_OK) return shape;
+    // Host-side planning reuses this thread's buffers from call to call.
+    thread_local std::vector<DevMsg> dm;
+    thread_local std::vector<Tile> tiles[2];
+    thread_local std::vector<uint32_t> cbc_list;
+    thread_local std::vector<Tile> cbc_groups;
+    thread_local std::vector<uint8_t> staging;
+    BatchTotals tot;
+    const int st = build_tiles(msgs, m, tile_blocks, dm, tiles, cbc_list, cbc_groups, tot);
+    if (st != AESGPU_OK) return st;
+    if (tiles[0].size() + tiles[1].size() + cbc_groups.size() == 0) return AESGPU_OK;
+    const int chk = check_run(tot, d_keys, n_key_slots, d_in, in_bytes, d_out, out_bytes);
+    if (chk != AESGPU_OK) return chk;
+    // Scratch layout, each part 256-byte aligned: queue counters (zero, as the
+    // batch kernel expects before a launch), messages, forward tiles, inverse
+    // tiles, CBC-encryption groups, 16 dummy bytes, CBC list.
+    const size_t o_msgs = align256(kCounterBytes);
+    const size_t o_t0 = o_msgs + align256(m * sizeof(DevMsg));
+    const size_t o_t1 = o_t0 + align256(tiles[0].size() * sizeof(Tile));
+    const size_t o_cg = o_t1 + align256(tiles[1].size() * sizeof(Tile));
+    const size_t o_dummy = o_cg + align256(cbc_groups.size() * sizeof(Tile));
+    const size_t o_cl = o_dummy + 256;
+    const size_t total = o_cl + cbc_list.size() * sizeof(uint32_t);
+    if (total > AESGPU_NOALLOC_SCRATCH_BYTES) return AESGPU_ESCRATCH;
+    staging.assign(total, 0);
+    uint8_t *h = staging.data();
+    if (m) std::memcpy(h + o_msgs, dm.data(), m * sizeof(DevMsg));
+    if (!tiles[0].empty()) std::memcpy(h + o_t0, tiles[0].data(), tiles[0].size() * sizeof(Tile));
+    if (!tiles[1].empty()) std::memcpy(h + o_t1, tiles[1].data(), tiles[1].size() * sizeof(Tile));
+    if (!cbc_groups.empty())
+        std::memcpy(h + o_cg, cbc_groups.data(), cbc_groups.size() * sizeof(Tile));
+    if (!cbc_list.empty())
+        std::memcpy(h + o_cl, cbc_list.data(), cbc_list.size() * sizeof(uint32_t));
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok()) return AESGPU_EHIP;
+    uint8_t *d = static_cast<uint8_t *>(scratch_address(ctx->device));
+    if (!d) return AESGPU_EHIP;
+    hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+    // From pageable host memory, so the copy has read `staging` when the
+    // call returns; it runs in stream order before the launches.
+    if (hipMemcpyAsync(d, h, total, hipMemcpyHostToDevice, s) != hipSuccess) return AESGPU_EHIP;
+    BatchLaunch L{};
+    L.msgs = reinterpret_cast<const DevMsg *>(d + o_msgs);
+    L.tiles[0] = reinterpret_cast<const Tile *>(d + o_t0);
+    L.tiles[1] = reinterpret_cast<const Tile *>(d + o_t1);
+    L.n_tiles[0] = uint32_t(tiles[0].size());
+    L.n_tiles[1] = uint32_t(tiles[1].size());
+    L.counters = reinterpret_cast<uint32_t *>(d);
+    L.keys = d_keys;
+    L.sched = nullptr;
+    L.in = static_cast<const uint8_t *>(d_in);
+    L.out = static_cast<uint8_t *>(d_out);
+    L.tables = ctx->d_tables;
+    L.cbc_list = reinterpret_cast<const uint32_t *>(d + o_cl);
+    L.cbc_groups = reinterpret_cast<const Tile *>(d + o_cg);
+    L.cbc_dummy = reinterpret_cast<uint4 *>(d + o_dummy);
+    L.n_cbc_groups = uint32_t(cbc_groups.size());
+    L.n_cu = ctx->n_cu;
+    L.bpl = bpl;
+    L.blocks[0] = tot.blocks[0];
+    L.blocks[1] = tot.blocks[1];
+    (void)use_graph;
+    return enqueue_batch(L, s);
 }
 
 }  // extern "C"

@@ -170,6 +170,7 @@ const char *aesgpu_strerror(int status) {
         case AESGPU_ENOMEM: return "out of memory";
         case AESGPU_EHIP: return "HIP runtime error";
         case AESGPU_EAGAIN: return "no free slot or memory; poll and retry";
+        case AESGPU_ESCRATCH: return "batch larger than the allocation-free call's fixed scratch";
         default: return "unknown status";
     }
 }
