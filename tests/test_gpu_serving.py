@@ -1,7 +1,8 @@
 """GPU tests of the continuous-batching server: every request's output equals
 the oracle's, the same request run alone gives the same bytes as in the mix
-(zero tolerance), a tiny arena forces slot reuse without corrupting outputs,
-and the trace replay reports consistent timestamps."""
+(zero tolerance), for small requests and over the served workload's whole
+64 B .. 16 MiB size range, a tiny arena forces slot reuse without corrupting
+outputs, and the trace replay reports consistent timestamps."""
 import time
 
 import numpy as np
@@ -168,5 +169,53 @@ def test_replay_poisson_trace(A, ctx, pool):
         lat = arr[:, 3] - arr[:, 1]
         log(f"replay: p50 {np.median(lat) * 1e6:.0f} us, p99 {np.quantile(lat, 0.99) * 1e6:.0f} us")
         assert A.aesgpu_server_get_stats(server).arena_used == 0
+    finally:
+        A.aesgpu_server_destroy(server)
+
+
+@pytest.fixture(scope="module")
+def full_range():
+    """Requests over the served workload's whole size range, 64 B .. 16 MiB
+    log-uniform, half encrypt and half decrypt, and the oracle's output for
+    every one of them."""
+    from paper_1201_0398_amd import workloads
+    tr = workloads.serving(rate_per_s=1000.0, n_requests=160, seed=24, n_keys=64, lo=64,
+                           hi=1 << 24, source_bytes=1 << 26)
+    log(f"oracle over {int(tr.sizes.sum())} bytes of requests up to {int(tr.sizes.max())} B")
+    return tr, [_expected(tr, j) for j in range(tr.sizes.size)]
+
+
+@pytest.mark.parametrize("direct", ["default", "never"])
+def test_full_size_range_in_mix_and_alone(A, ctx, full_range, direct):
+    """The batched server over 64 B .. 16 MiB requests: every output in the
+    mix equals the oracle's, and requests run alone (the 12 largest and 28
+    others) give the same bytes as in the mix."""
+    import torch
+    tr, want = full_range
+    n = tr.sizes.size
+    src = torch.from_numpy(tr.source.copy()).to("cuda")
+    base = src.data_ptr()
+    server = A.aesgpu_server_create(
+        ctx, tr.pool_keys, tr.pool_bits, arena_bytes=1 << 30,
+        direct_requests=A.AESGPU_SERVER_NO_DIRECT if direct == "never" else 0)
+    try:
+        log(f"case: {n} requests of 64 B..16 MiB at once, direct={direct}")
+        mix = {}
+        for j in range(n):
+            A.aesgpu_server_submit(server, j, int(tr.dirs[j]), int(tr.key_ids[j]),
+                                   base + int(tr.src_offsets[j]), int(tr.sizes[j]))
+        _drain(A, server, n, mix)
+        assert A.aesgpu_server_get_stats(server).arena_used == 0
+        for j in range(n):
+            assert np.array_equal(mix[j], want[j]), f"request {j} ({tr.sizes[j]} B) in the mix"
+        order = np.argsort(tr.sizes)
+        alone_ids = np.unique(np.concatenate([order[-12:], np.arange(28)]))
+        log(f"case: {alone_ids.size} of them alone, direct={direct}")
+        for j in alone_ids:
+            alone = {}
+            A.aesgpu_server_submit(server, int(j), int(tr.dirs[j]), int(tr.key_ids[j]),
+                                   base + int(tr.src_offsets[j]), int(tr.sizes[j]))
+            _drain(A, server, 1, alone)
+            assert np.array_equal(alone[int(j)], mix[int(j)]), f"request {j}: alone != in the mix"
     finally:
         A.aesgpu_server_destroy(server)
