@@ -605,14 +605,18 @@ static void *thread_main(void *arg)
     return NULL;
 }
 
+/* Threads only partition the block range; a request for more than this is
+   clamped to it (the job and thread arrays live on the stack). */
+#define ORACLE_MAX_THREADS 512
+
 static int resolve_threads(int threads, size_t n_blocks)
 {
     if (threads <= 0) {
         long n = sysconf(_SC_NPROCESSORS_ONLN);
         threads = (n > 0) ? (int)n : 1;
     }
-    if (threads > 64)
-        threads = 64;
+    if (threads > ORACLE_MAX_THREADS)
+        threads = ORACLE_MAX_THREADS;
     if ((size_t)threads > n_blocks)
         threads = n_blocks ? (int)n_blocks : 1;
     return threads;
@@ -628,8 +632,8 @@ static int run_mode(const job_t *proto, size_t n_blocks, int threads)
         run_blocks(&j);
         return ORACLE_OK;
     }
-    pthread_t tid[64];
-    job_t jobs[64];
+    pthread_t tid[ORACLE_MAX_THREADS];
+    job_t jobs[ORACLE_MAX_THREADS];
     int started = 0;
     for (int t = 0; t < threads; t++) {
         jobs[t] = *proto;

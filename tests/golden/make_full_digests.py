@@ -1,0 +1,117 @@
+"""Writes ``full_size_digests.json``: SHA-256 digests of the CPU oracle's
+outputs over the whole full-size workloads, so that a GPU test can compare
+every output byte with the oracle without re-running the (slow, literal)
+oracle on the GPU machine.
+
+Workloads (``paper_1201_0398_amd.workloads``):
+
+* 1 GiB, seed 1: ECB encryption and ECB decryption of the random buffer with
+  each of the three keys, and AES-128 CTR (nonce || BE32 counter from 1);
+* 4 GiB, seed 2: AES-256 CTR from counter 1, in 256 MiB chunks (the counter
+  advances by 2^24 per chunk);
+* 65,536 messages, seed 3: the packed output buffer of the encryption run
+  and of the decryption run (every message decrypted: ECB messages through
+  the inverse cipher, CTR messages through the same keystream).
+
+Calls only the oracle and the seeded input generators.  Takes about half an
+hour on 8 cores.  Run from the repository root:
+``python tests/golden/make_full_digests.py [--only NAME ...]``.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_1201_0398_amd import workloads  # noqa: E402
+
+OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "full_size_digests.json")
+CHUNK = 1 << 28   # 256 MiB = 2^24 blocks
+
+
+def sha(a) -> str:
+    return hashlib.sha256(memoryview(np.ascontiguousarray(a))).hexdigest()
+
+
+def log(msg: str) -> None:
+    print(f"[{time.strftime('%H:%M:%S')}] {msg}", flush=True)
+
+
+def gib1(out: dict) -> None:
+    w = workloads.single_1gib(seed=1)
+    out["gib1_input_sha256"] = sha(w.data)
+    for bits in (128, 192, 256):
+        key = w.keys[bits]
+        log(f"1 GiB ECB-{bits} encrypt")
+        out[f"gib1_ecb{bits}_encrypt_sha256"] = sha(oracle.ecb_encrypt(key, w.data))
+        log(f"1 GiB ECB-{bits} decrypt")
+        out[f"gib1_ecb{bits}_decrypt_sha256"] = sha(oracle.ecb_decrypt(key, w.data))
+    log("1 GiB CTR-128")
+    out["gib1_ctr128_sha256"] = sha(oracle.ctr(w.keys[128], w.nonce, w.ctr0, w.data))
+
+
+def gib4(out: dict) -> None:
+    w = workloads.ctr_4gib(seed=2)
+    out["gib4_input_sha256"] = sha(w.data)
+    h = hashlib.sha256()
+    for i, o in enumerate(range(0, w.data.size, CHUNK)):
+        log(f"4 GiB CTR-256 chunk {i}")
+        h.update(memoryview(oracle.ctr(w.keys[256], w.nonce, w.ctr0 + i * (CHUNK // 16),
+                                       w.data[o:o + CHUNK])))
+    out["gib4_ctr256_sha256"] = h.hexdigest()
+
+
+def batched(out: dict) -> None:
+    w = workloads.batched(seed=3)
+    m = w.lengths.size
+    out["batched_input_sha256"] = sha(w.data)
+    out["batched_total_bytes"] = int(w.total_bytes)
+    enc = np.empty_like(w.data)
+    dec = np.empty_like(w.data)
+    t0 = time.time()
+    for j in range(m):
+        o, L = int(w.offsets[j]), int(w.lengths[j])
+        key = w.keys[j, : int(w.key_bits[j]) // 8]
+        src = w.data[o:o + L]
+        if w.modes[j]:
+            enc[o:o + L] = oracle.ctr(key, w.nonces[j], int(w.ctr0[j]), src)
+            dec[o:o + L] = enc[o:o + L]
+        else:
+            enc[o:o + L] = oracle.ecb_encrypt(key, src)
+            dec[o:o + L] = oracle.ecb_decrypt(key, src)
+        if j % 8192 == 8191:
+            log(f"batched: {j + 1} of {m} messages ({time.time() - t0:.0f} s)")
+    out["batched_encrypt_sha256"] = sha(enc)
+    out["batched_decrypt_sha256"] = sha(dec)
+
+
+PARTS = {"gib1": gib1, "gib4": gib4, "batched": batched}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--only", nargs="*", choices=sorted(PARTS), default=sorted(PARTS))
+    args = ap.parse_args()
+    out = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            out = json.load(f)
+    out["recipe"] = ("workloads.single_1gib(seed=1), workloads.ctr_4gib(seed=2), "
+                     "workloads.batched(seed=3); digests of whole oracle outputs")
+    for name in args.only:
+        PARTS[name](out)
+        with open(OUT, "w") as f:
+            json.dump(out, f, indent=1, sort_keys=True)
+            f.write("\n")
+        log(f"{name} written")
+
+
+if __name__ == "__main__":
+    main()

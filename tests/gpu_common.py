@@ -59,3 +59,24 @@ def copy_device(dst: int, src: int, n: int) -> None:
     hip.hipMemcpy.restype = ctypes.c_int
     rc = hip.hipMemcpy(dst, src, n, 3)  # hipMemcpyDeviceToDevice
     assert rc == 0, f"hipMemcpy failed: {rc}"
+
+
+def sha256_dev(t, chunk: int = 1 << 28) -> str:
+    """SHA-256 of a device uint8 tensor's bytes, copied to the host in chunks."""
+    import hashlib
+    h = hashlib.sha256()
+    n = t.numel()
+    for o in range(0, n, chunk):
+        h.update(memoryview(t[o:o + chunk].cpu().numpy()))
+    return h.hexdigest()
+
+
+def full_size_digests() -> dict:
+    """Digests of the oracle's whole outputs on the full-size workloads,
+    written by tests/golden/make_full_digests.py from the oracle alone."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                        "full_size_digests.json")
+    with open(path) as f:
+        return json.load(f)

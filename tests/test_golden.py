@@ -27,3 +27,12 @@ def test_oracle_digests_small_workload():
     assert _sha(oracle.ctr_le128(key, w.iv, 0, w.data)) == g["ctr_le128_index0_0_sha256"]
     assert _sha(oracle.cbc_encrypt(key, w.iv, w.data)) == g["cbc128_encrypt_sha256"]
     assert _sha(oracle.cbc_decrypt(key, w.iv, w.data)) == g["cbc128_decrypt_of_input_sha256"]
+
+
+def test_full_size_input_recipe():
+    """The 1 GiB workload's input still hashes to the digest the full-size
+    oracle digests were computed on (golden/full_size_digests.json)."""
+    with open(os.path.join(os.path.dirname(GOLDEN), "full_size_digests.json")) as f:
+        g = json.load(f)
+    w = workloads.single_1gib(seed=1)
+    assert hashlib.sha256(memoryview(w.data)).hexdigest() == g["gib1_input_sha256"]

@@ -1,7 +1,8 @@
 """GPU parity of the batched persistent launch: every message of a mixed batch
 (own key, key size, mode, direction, uneven length) against the CPU oracle run
 on that message alone; graph replays against direct launches; the full
-65,536-message workload by sampled messages plus the whole-batch round trip."""
+65,536-message workload compared in full with the oracle in both directions
+(digests of the whole outputs) plus the whole-batch round trip."""
 import numpy as np
 import pytest
 
@@ -297,13 +298,23 @@ def test_plan_and_run_errors(A, ctx):
 
 def test_full_batched_workload(A, ctx):
     """65,536 messages, 16 B .. 1 MiB log-uniform, seed 3: one encrypt run and
-    one decrypt run; 2,000 random messages (plus the 50 longest and 50
-    shortest) checked against the oracle, and the whole batch round-trips."""
+    one decrypt run of the random input, each compared in full with the
+    oracle (the SHA-256 of the whole packed output equals the digest of the
+    oracle's, from golden/full_size_digests.json); 2,000 random messages plus
+    the 50 longest and 50 shortest are also recomputed by the oracle one by
+    one, to name a wrong message; and the whole batch round-trips."""
+    import hashlib
+
     import torch
+    from gpu_common import full_size_digests, sha256_dev
     from paper_1201_0398_amd import workloads
     log("case: batched workload seed 3 (generating)")
+    g = full_size_digests()
     w = workloads.batched(seed=3)
     m = w.lengths.size
+    assert w.total_bytes == g["batched_total_bytes"]
+    assert hashlib.sha256(memoryview(w.data)).hexdigest() == g["batched_input_sha256"], \
+        "the batched input recipe changed"
     log(f"{m} messages, {w.total_bytes} bytes")
     zeros = np.zeros(m, dtype=np.int64)
     enc = A.make_msgs(w.offsets, w.offsets, w.lengths, np.arange(m), w.key_bits, w.modes, zeros,
@@ -327,7 +338,11 @@ def test_full_batched_workload(A, ctx):
             want = oracle.ctr(key, w.nonces[j], 1, src) if w.modes[j] else oracle.ecb(key, src)
             got = from_dev(d_ct[o:o + L])
             assert np.array_equal(got, want), f"message {j} (len {L}, mode {w.modes[j]})"
+        assert sha256_dev(d_ct) == g["batched_encrypt_sha256"], "batched encryption output"
+        log("case: batched workload, decryption of the random input")
         d_pt = torch.empty_like(d_in)
+        A.aesgpu_batch_run(pd, d_keys, m, d_in, d_pt)
+        assert sha256_dev(d_pt) == g["batched_decrypt_sha256"], "batched decryption output"
         A.aesgpu_batch_run(pd, d_keys, m, d_ct, d_pt)
         assert torch.equal(d_pt, d_in), "batch round trip failed"
     finally:

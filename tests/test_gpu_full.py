@@ -1,13 +1,19 @@
-"""GPU parity at the full workload sizes (1 GiB per key size; 4 GiB CTR),
-in the launch configuration the benchmark times.  The oracle recomputes
-sampled blocks one by one (both ends, random positions, tile and grid-stride
-edges); properties that hold at any size (decrypt(encrypt(x)) = x, CTR is its
-own inverse) are checked on the whole buffer on the GPU."""
+"""GPU parity at the full workload sizes (1 GiB per key size; 4 GiB CTR), in
+the launch configuration the benchmark times.  Every output byte is compared
+with the oracle: the SHA-256 of the whole GPU output equals the digest of the
+oracle's whole output (``golden/full_size_digests.json``, written by
+``golden/make_full_digests.py`` from the oracle alone; the oracle takes about
+half an hour over these workloads, so it is not re-run here).  The input's
+digest is checked first, so a change in the input recipe shows as such.
+Sampled blocks are also recomputed by the oracle one by one (both ends,
+random positions, tile and grid-stride edges), to name the first wrong block
+if a digest differs."""
 import numpy as np
 import pytest
 
 import oracle
-from gpu_common import gather_blocks, log, requires_gpu, sample_indices, to_dev
+from gpu_common import (full_size_digests, gather_blocks, log, requires_gpu, sample_indices,
+                        sha256_dev, to_dev)
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -29,16 +35,26 @@ def ctx(A):
 
 
 @pytest.fixture(scope="module")
-def gib():
+def digests():
+    return full_size_digests()
+
+
+@pytest.fixture(scope="module")
+def gib(digests):
+    import hashlib
+
     from paper_1201_0398_amd import workloads
     log("generating 1 GiB workload (seed 1)")
-    return workloads.single_1gib(seed=1)
+    w = workloads.single_1gib(seed=1)
+    assert hashlib.sha256(memoryview(w.data)).hexdigest() == digests["gib1_input_sha256"], \
+        "the 1 GiB input recipe changed"
+    return w
 
 
 @pytest.mark.parametrize("bits", [128, 192, 256])
-def test_1gib_ecb(A, ctx, gib, bits):
+def test_1gib_ecb(A, ctx, gib, digests, bits):
     import torch
-    log(f"case: 1 GiB ECB-{bits}")
+    log(f"case: 1 GiB ECB-{bits}, whole buffer both ways")
     key = gib.keys[bits]
     k = A.aesgpu_expand_key(key)
     n = gib.data.size // 16
@@ -47,19 +63,20 @@ def test_1gib_ecb(A, ctx, gib, bits):
     A.aesgpu_ecb_encrypt(ctx, k, d_in, d_ct)
     rng = np.random.default_rng(bits)
     idx = sample_indices(n, rng, boundaries=[TILE, GRID_STEP, n - GRID_STEP])
-    got = gather_blocks(d_ct, idx)
-    assert np.array_equal(got, oracle.ecb_sampled(key, gib.data, idx))
+    assert np.array_equal(gather_blocks(d_ct, idx), oracle.ecb_sampled(key, gib.data, idx))
+    assert sha256_dev(d_ct) == digests[f"gib1_ecb{bits}_encrypt_sha256"]
     d_pt = torch.empty_like(d_in)
     A.aesgpu_ecb_decrypt(ctx, k, d_ct, d_pt)
     assert torch.equal(d_pt, d_in), "decrypt(encrypt(x)) != x"
     A.aesgpu_ecb_decrypt(ctx, k, d_in, d_pt)
-    got = gather_blocks(d_pt, idx)
-    assert np.array_equal(got, oracle.ecb_sampled(key, gib.data, idx, decrypt=True))
+    assert np.array_equal(gather_blocks(d_pt, idx),
+                          oracle.ecb_sampled(key, gib.data, idx, decrypt=True))
+    assert sha256_dev(d_pt) == digests[f"gib1_ecb{bits}_decrypt_sha256"]
 
 
-def test_1gib_ctr128(A, ctx, gib):
+def test_1gib_ctr128(A, ctx, gib, digests):
     import torch
-    log("case: 1 GiB CTR-128")
+    log("case: 1 GiB CTR-128, whole buffer")
     key = gib.keys[128]
     k = A.aesgpu_expand_key(key)
     n = gib.data.size // 16
@@ -69,15 +86,20 @@ def test_1gib_ctr128(A, ctx, gib):
     idx = sample_indices(n, np.random.default_rng(5), boundaries=[TILE, GRID_STEP])
     got = gather_blocks(d_out, idx)
     assert np.array_equal(got, oracle.ctr_sampled(key, gib.nonce, gib.ctr0, gib.data, idx))
+    assert sha256_dev(d_out) == digests["gib1_ctr128_sha256"]
     A.aesgpu_ctr_xcrypt(ctx, k, gib.nonce, gib.ctr0, d_out, d_out)
     assert torch.equal(d_out, d_in)
 
 
-def test_4gib_ctr256(A, ctx):
+def test_4gib_ctr256(A, ctx, digests):
+    import hashlib
+
     import torch
     from paper_1201_0398_amd import workloads
     log("case: 4 GiB CTR-256 seed 2 (generating)")
     w = workloads.ctr_4gib(seed=2)
+    assert hashlib.sha256(memoryview(w.data)).hexdigest() == digests["gib4_input_sha256"], \
+        "the 4 GiB input recipe changed"
     key = w.keys[256]
     k = A.aesgpu_expand_key(key)
     n = w.data.size // 16
@@ -87,5 +109,6 @@ def test_4gib_ctr256(A, ctx):
     idx = sample_indices(n, np.random.default_rng(6), boundaries=[1 << 24, 1 << 27, GRID_STEP])
     got = gather_blocks(d_out, idx)
     assert np.array_equal(got, oracle.ctr_sampled(key, w.nonce, w.ctr0, w.data, idx))
+    assert sha256_dev(d_out) == digests["gib4_ctr256_sha256"], "4 GiB CTR-256 output"
     A.aesgpu_ctr_xcrypt(ctx, k, w.nonce, w.ctr0, d_out, d_out)
     assert torch.equal(d_out, d_in), "CTR(CTR(x)) != x over 4 GiB"
