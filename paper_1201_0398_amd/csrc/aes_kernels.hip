@@ -26,9 +26,12 @@
 //  * 1024 threads per workgroup and one workgroup per CU (the tables take the
 //    whole LDS); the grid is at most one workgroup per CU and strides over
 //    tiles of 1024 * BPL blocks.  BPL is 4 when every CU gets a full tile and
-//    smaller for smaller buffers (every slot of a tile is computed).
+//    smaller for smaller buffers (every slot of a tile is computed); at one
+//    block per lane a small buffer is cut into tiles of 64..1024 blocks, one
+//    per CU, and the waves past a tile's end leave after the table staging.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdlib>
 
 #include "aes_device.h"
@@ -49,6 +52,8 @@ struct Params {
     uint64_t index0;        // LE-128 counter offset
     uint32_t ctr_y;         // LE-128: word 0 of the counter of virtual slot 0
     uint32_t voff;          // virtual index = block index + voff (CTR: ctr0 mod 64 * BPL)
+    uint32_t tile;          // blocks per tile: kWG * BPL, or a multiple of 64 below kWG
+                            // for small buffers at 1 block per lane
     uint32_t iv[4];
     CtrConsts cc;
     RoundKeys rk;
@@ -159,7 +164,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
 
     // The loop covers the whole blocks; a CTR tail is finished after it.
     const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
-    const uint64_t tile = uint64_t(kWG) * BPL;
+    const uint64_t tile = p.tile;
     const uint64_t stride = uint64_t(gridDim.x) * tile;
     const uint32_t wave_first = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
     // The blocks of the next tile are loaded while the current one is
@@ -174,6 +179,9 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         next_prev = load_wave_prev<BPL>(p.in, uint64_t(blockIdx.x) * tile, wave_first, p.n_full,
                                         uint32_t(tile));
     stage_tables<kInv>(lds, p.tables);
+    // A small tile leaves the workgroup's last waves without blocks in every
+    // tile: they end here (the staging barrier was the last one).
+    if (wave_first * BPL >= p.tile) return;
     const Bases b = lane_bases();
     // In the loop a tile's loads are followed by the previous tile's stores,
     // and the loop top waits for the loads only.  These stores have an empty
@@ -349,7 +357,17 @@ int launch_one(Params p, int n_cu, hipStream_t stream) {
     }
     // At least one workgroup: a CTR call shorter than a block has only a tail.
     const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
-    const uint64_t tiles = (v_end + uint64_t(kWG) * BPL - 1) / (uint64_t(kWG) * BPL);
+    // Tiles of kWG * BPL blocks; at one block per lane (small buffers) the
+    // blocks are spread over every CU instead, in tiles of a multiple of 64
+    // blocks (whole waves): a small call then costs the table staging and a
+    // few waves' rounds per CU rather than a whole 1024-block tile on a few.
+    uint64_t tile = uint64_t(kWG) * BPL;
+    if (BPL == 1) {
+        const uint64_t per_cu = (v_end + uint64_t(n_cu) - 1) / uint64_t(n_cu);
+        tile = std::min<uint64_t>(kWG, std::max<uint64_t>(64, (per_cu + 63) & ~uint64_t(63)));
+    }
+    p.tile = uint32_t(tile);
+    const uint64_t tiles = (v_end + tile - 1) / tile;
     const uint32_t grid = tiles == 0 ? 1u : uint32_t(tiles < uint64_t(n_cu) ? tiles : uint64_t(n_cu));
     // The launch's own status (the thread's last-error state may hold an
     // earlier, unrelated failure).
