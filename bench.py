@@ -10,7 +10,8 @@ of the same workload on the host cores.
 Warm-up: W untimed steps, extended until --min-warmup-s (default 0.3 s) of
 back-to-back work has passed, since the GPU clock ramps up over tens of
 milliseconds of sustained load; the timed steps follow with no other GPU work
-in between.  The JSON line's "warmup" is the number of warm-up steps run.
+in between.  The JSON line's "warmup" is W as asked for; "warmup_steps_run"
+and "warmup_s_run" are the steps and seconds actually run.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
        python bench.py --copy-calibration   (plain 1 GiB device copies, for
@@ -35,6 +36,7 @@ HBM_PEAK_GBS = 8000.0
 LDS_READS_PER_BLOCK = {"ecb_encrypt": 160, "ecb_decrypt": 160, "ctr_xcrypt": 133}
 LDS_PEAK_TREADS = 256 * 32 * 2.4e9 / 1e12
 GIB = 1 << 30
+SERVE_SOURCE_BYTES = 2 * GIB
 
 
 HBM_SUMMARY = os.path.join(ROOT, "profiles", "aes128_1gib_hbm_bytes.md")
@@ -85,6 +87,9 @@ def parse():
     ap.add_argument("--no-pipeline", action="store_true")
     ap.add_argument("--no-cbc-batch", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=100000)
+    ap.add_argument("--only-sizes", action="store_true",
+                    help="time only AES-128 ECB encryption calls of 16 KiB..1 GiB (the per-call "
+                         "floor of small buffers) and print them as one JSON line")
     return ap.parse_args()
 
 
@@ -224,7 +229,11 @@ def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None, fla
     # GB, so a 4 GiB arena fills and starves admission; 16 GiB is under 6%
     # of the device memory.
     arena = 16 << 30
-    tr = workloads.serving(rate_per_s=1.0, n_requests=n_requests, seed=4, source_bytes=1 << 28)
+    # Request inputs are slices of a 2 GiB device-resident source pool, eight
+    # times the 256 MB Infinity Cache, so that they stream from HBM as the
+    # single-buffer runs they are compared with do.
+    tr = workloads.serving(rate_per_s=1.0, n_requests=n_requests, seed=4,
+                           source_bytes=SERVE_SOURCE_BYTES)
     std_gaps = np.diff(np.concatenate([[0.0], tr.arrivals]))  # Exp(1) gaps: scale per rate
     total = int(tr.sizes.sum())
     src = torch.from_numpy(tr.source.copy()).to("cuda")
@@ -276,10 +285,11 @@ def serving_bench(torch, A, ctx, n_requests: int, rates: dict | None = None, fla
     return {**extra, "saturation_GB_s": round(total / (n_requests / lam_sat) / 1e9, 1),
             "saturation_req_s": round(lam_sat, 1), "requests_per_point": n_requests,
             "mean_request_bytes": round(total / n_requests, 1), "arena_bytes": arena,
+            "source_pool_bytes": SERVE_SOURCE_BYTES,
             "batches": int(st.batches), "points": points,
             "workload": "Poisson arrivals, ECB requests 64 B..16 MiB log-uniform, 50/50 "
                         "encrypt/decrypt, 1,024 resident keys of mixed size, seed 4; inputs "
-                        "device-resident; latency = completion seen by the host - arrival; "
+                        "device-resident slices of a 2 GiB pool; latency = completion seen by the host - arrival; "
                         "each point: median over three replays, with the worst p99 and "
                         "lowest GB/s of the three"}
 
@@ -388,12 +398,36 @@ def pipeline_bench(torch, A, ctx, key_bytes: bytes) -> dict:
     return out
 
 
+def host_cores() -> dict:
+    """The host CPU as this process sees it: cores online, cores it may run
+    on, the CPU share the machine grants one GPU's jobs (its OMP_NUM_THREADS,
+    where set) and the model name."""
+    nproc = os.cpu_count() or 1
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        affinity = nproc
+    share = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or affinity
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
+                         "")
+    except OSError:
+        pass
+    return {"nproc": nproc, "affinity": affinity, "share": min(share, affinity), "model": model}
+
+
 def cpu_baseline(sample_bytes: int) -> dict:
+    """The oracle on every core of this process's CPU share: the host's
+    OMP_NUM_THREADS where the machine sets it (its share of host cores per
+    GPU), else every core the process may run on."""
     import numpy as np
 
     import oracle
     from paper_1201_0398_amd import workloads
-    threads = min(os.cpu_count() or 1, 16)
+    host = host_cores()
+    threads = host["share"]
     w = workloads.single_1gib(seed=1, n_bytes=sample_bytes)
     key = w.keys[128]
     t0 = time.perf_counter()
@@ -412,21 +446,16 @@ def cpu_baseline(sample_bytes: int) -> dict:
     tt = time.perf_counter()
     oracle.ttable_ecb(key, w.data[:nt])
     tt = time.perf_counter() - tt
-    model = ""
-    try:
-        with open("/proc/cpuinfo") as f:
-            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")),
-                         "")
-    except OSError:
-        pass
     return {"value": round(3 * sample_bytes / dt / 1e9, 6), "unit": "GB/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"AES-128 ECB encrypt + ECB decrypt + CTR of the first {sample_bytes >> 20} "
-                      f"MiB of the 1 GiB seed-1 workload, literal FIPS-197 oracle, "
-                      f"{threads} threads, {dt:.1f} s",
-            "one_core_GB_s": {"literal_ecb_encrypt_1MiB": round(n1 / t1 / 1e9, 6),
-                              "ttable_ecb_encrypt_16MiB": round(nt / tt / 1e9, 6)},
-            "host_cpu": model}
+            "sample": f"AES-128 ECB enc+dec+CTR of the first {sample_bytes >> 20} MiB of the "
+                      f"1 GiB seed-1 buffer, literal oracle, {threads} threads, {dt:.1f} s",
+            "one_core_literal_GB_s": round(n1 / t1 / 1e9, 6),
+            "one_core_ttable_GB_s": round(nt / tt / 1e9, 6),
+            "host_nproc": host["nproc"], "host_affinity_cores": host["affinity"],
+            "host_cpu": host["model"][:100],
+            "cores_note": "threads = the host's OMP_NUM_THREADS (its CPU share per GPU) or "
+                          "every core this process may run on"}
 
 
 def main() -> int:
@@ -441,6 +470,17 @@ def main() -> int:
 
     if args.copy_calibration:
         copy_calibration(torch, args.bytes)
+        return 0
+    if args.only_sizes:
+        from paper_1201_0398_amd import aesgpu as A
+        from paper_1201_0398_amd import workloads
+        w = workloads.single_1gib(seed=1, n_bytes=args.bytes)
+        d_in = torch.from_numpy(w.data).to("cuda")
+        d_out = torch.empty_like(d_in)
+        ctx = A.aesgpu_create()
+        rows = size_sweep(torch, A, ctx, w, d_in, d_out)
+        A.aesgpu_destroy(ctx)
+        print(json.dumps({"single_buffer_sizes_aes128_ecb_enc": rows}), flush=True)
         return 0
 
     from paper_1201_0398_amd import aesgpu as A
@@ -490,7 +530,9 @@ def main() -> int:
         if warm % 8 == 0:
             torch.cuda.synchronize()
     torch.cuda.synchronize()
-    log(f"warmed up with {warm} steps; timing {args.steps} steps")
+    warm_s = time.perf_counter() - t_w
+    log(f"warmed up with {warm} steps ({args.warmup} asked for) in {warm_s:.2f} s; "
+        f"timing {args.steps} steps")
     t0 = time.perf_counter()
     for _ in range(args.steps):
         step(True)
@@ -508,7 +550,8 @@ def main() -> int:
                   for n in names}
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "GB/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": warm, "ms_per_step": round(ms_step, 4),
+        "steps": args.steps, "warmup": args.warmup, "warmup_steps_run": warm,
+        "warmup_s_run": round(warm_s, 3), "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": "AES-128 ECB encrypt + ECB decrypt + CTR (nonce||BE32, ctr0=1) of "
