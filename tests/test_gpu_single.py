@@ -359,3 +359,45 @@ def test_threads_and_streams_share_one_context(A, ctx):
     for j in jobs:
         assert np.array_equal(j["enc"], oracle.ecb_encrypt(j["key"], j["data"]))
         assert np.array_equal(j["ctr"], oracle.ctr(j["key"], j["nonce"], 7, j["data"]))
+
+
+def test_small_buffer_tiles_every_mode(A, ctx):
+    """Buffers in the one-block-per-lane range, which the kernel cuts into
+    tiles of 64..1024 blocks, one per CU: sizes whose tiles are 64, 128, 320
+    and 1024 blocks with ragged ends, one whose tiles make the grid stride,
+    and the top of the range; every mode against the oracle, guard bytes
+    after each output untouched."""
+    import torch
+    n_cu = A.aesgpu_ctx_num_cus(ctx)
+    rng = np.random.default_rng(6100)
+    key = rng.integers(0, 256, 16, dtype=np.uint8)
+    k = A.aesgpu_expand_key(key)
+    sizes = [n_cu * 64 - 5, n_cu * 128 - 1, n_cu * 300 + 5, n_cu * 1024 - 7, n_cu * 1024 + 3,
+             n_cu * 2048 - 1]
+    for n in sizes:
+        data = rng.integers(0, 256, 16 * n, dtype=np.uint8)
+        d_in = to_dev(data)
+        d_out = torch.full((16 * n + 64,), 0x5A, dtype=torch.uint8, device="cuda")
+        iv = rng.integers(0, 256, 16, dtype=np.uint8)
+        nonce = rng.integers(0, 256, 12, dtype=np.uint8)
+        ctr0 = int(rng.integers(0, 1 << 30))
+        cases = [
+            ("ecb enc", lambda: A.aesgpu_ecb_encrypt(ctx, k, d_in, d_out, n),
+             lambda: oracle.ecb_encrypt(key, data)),
+            ("ecb dec", lambda: A.aesgpu_ecb_decrypt(ctx, k, d_in, d_out, n),
+             lambda: oracle.ecb_decrypt(key, data)),
+            ("ctr", lambda: A.aesgpu_ctr_xcrypt(ctx, k, nonce, ctr0, d_in, d_out, 16 * n - 3),
+             lambda: oracle.ctr(key, nonce, ctr0, data[:16 * n - 3])),
+            ("ctr le128", lambda: A.aesgpu_ctr_le128_xcrypt(ctx, k, iv, 77, d_in, d_out, 16 * n),
+             lambda: oracle.ctr_le128(key, iv, 77, data)),
+            ("cbc dec", lambda: A.aesgpu_cbc_decrypt(ctx, k, iv, d_in, d_out, n),
+             lambda: oracle.cbc_decrypt(key, iv, data)),
+        ]
+        for name, run, want in cases:
+            log(f"case: small-buffer tiles, {name}, n_blocks={n}")
+            d_out.fill_(0x5A)
+            run()
+            w = want()
+            out = from_dev(d_out)
+            assert np.array_equal(out[:w.size], w), f"{name} n_blocks={n}"
+            assert (out[w.size:] == 0x5A).all(), f"{name} n_blocks={n}: wrote past the end"
