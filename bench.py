@@ -166,6 +166,17 @@ def size_sweep(torch, A, ctx, w, d_in, d_out) -> list:
     return rows
 
 
+def launch_floor(torch) -> dict:
+    """The per-call floor of any kernel launched from Python back to back:
+    torch's own elementwise add on a 16-byte tensor, timed like the AES calls."""
+    tiny = torch.zeros(4, device="cuda")
+    call = lambda: tiny.add_(1.0)  # noqa: E731
+    time_call(torch, call, 2000)
+    t = time_call(torch, call, 2000)
+    return {"torch_add_16B_us": round(t * 1e6, 2),
+            "what": "torch add_ on a 16-byte device tensor, back to back, HIP events"}
+
+
 def batched_bench(torch, A, ctx, rates: dict, reps: int, warm_s: float) -> dict:
     """The 65,536-message batch (seed 3), encrypt direction, graph replays."""
     import numpy as np
@@ -480,7 +491,8 @@ def main() -> int:
         ctx = A.aesgpu_create()
         rows = size_sweep(torch, A, ctx, w, d_in, d_out)
         A.aesgpu_destroy(ctx)
-        print(json.dumps({"single_buffer_sizes_aes128_ecb_enc": rows}), flush=True)
+        print(json.dumps({"single_buffer_sizes_aes128_ecb_enc": rows,
+                          "launch_floor": launch_floor(torch)}), flush=True)
         return 0
 
     from paper_1201_0398_amd import aesgpu as A
@@ -591,6 +603,7 @@ def main() -> int:
         rates = single_rates(torch, A, ctx, w, d_in, d_ct)
         out["single_buffer_GB_s"] = {f"aes{b}_{m}": round(v / 1e9, 1) for (b, m), v in rates.items()}
         out["single_buffer_sizes_aes128_ecb_enc"] = size_sweep(torch, A, ctx, w, d_in, d_ct)
+        out["launch_floor"] = launch_floor(torch)
         del d_pt, d_ctr
         out["batched"] = batched_bench(torch, A, ctx, rates, args.batched_reps, args.min_warmup_s)
     if not args.no_serving:
