@@ -78,8 +78,10 @@ typedef struct {
  * Creates a context on HIP device `device`: builds the lookup tables T0..T3,
  * their inverses and the S-boxes on the host and copies them to the device
  * once (the paper's section 3 creates all resources once at start-up).
- * *out receives the context.  Errors: EINVAL (out NULL, bad device), ENOMEM,
- * EHIP.
+ * *out receives the context.  The single-buffer calls choose their blocks per
+ * lane by size; the environment variable AESGPU_FORCE_BPL=1, 2 or 4, read
+ * here, fixes it for this context's calls (for tests and measurements).
+ * Errors: EINVAL (out NULL, bad device), ENOMEM, EHIP.
  */
 int aesgpu_create(aesgpu_ctx **out, int device);
 

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cstdlib>
 #include <cstring>
 
 #include "aes_internal.h"
@@ -130,7 +131,9 @@ CtrConsts ctr_consts(const aesgpu_key *key, const uint32_t (&x)[4], int var, Ctr
 int run(aesgpu_ctx *ctx, const LaunchArgs &a, aesgpu_stream_t stream) {
     DeviceGuard g(ctx->device);
     if (!g.ok()) return AESGPU_EHIP;
-    return launch(ctx->d_tables, ctx->n_cu, a, reinterpret_cast<hipStream_t>(stream));
+    LaunchArgs b = a;
+    b.bpl = ctx->blocks_per_lane;
+    return launch(ctx->d_tables, ctx->n_cu, b, reinterpret_cast<hipStream_t>(stream));
 }
 
 }  // namespace
@@ -220,7 +223,14 @@ int aesgpu_create(aesgpu_ctx **out, int device) {
     if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess ||
         n_cu <= 0)
         return AESGPU_EHIP;
-    aesgpu_ctx *ctx = new (std::nothrow) aesgpu_ctx{device, n_cu, nullptr};
+    // AESGPU_FORCE_BPL=1|2|4 fixes the single-buffer launches' blocks per lane
+    // for this context (tests use it to run every kernel variant).
+    int bpl = 0;
+    if (const char *e = std::getenv("AESGPU_FORCE_BPL")) {
+        const int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4) bpl = v;
+    }
+    aesgpu_ctx *ctx = new (std::nothrow) aesgpu_ctx{device, n_cu, nullptr, bpl};
     if (!ctx) return AESGPU_ENOMEM;
     const HostTables &t = host_tables();
     if (hipMalloc(&ctx->d_tables, sizeof(t.words)) != hipSuccess) {

@@ -63,6 +63,7 @@ struct LaunchArgs {
     uint32_t ctr0;        // kCtrBe32 only
     uint32_t iv[4];       // kCtrLe128 (counter of block 0), kCbcDec (IV words)
     uint64_t index0;      // kCtrLe128: added to iv (0 from the host's own calls)
+    int bpl;              // blocks per lane: 1, 2 or 4, or 0 to choose by size
 };
 
 // Enqueues the kernel for `a` on `stream`; returns an AESGPU status.
@@ -100,4 +101,6 @@ struct aesgpu_ctx {
     int device;
     int n_cu;
     uint32_t *d_tables;
+    int blocks_per_lane;   // single-buffer launches: 1, 2 or 4 (AESGPU_FORCE_BPL at
+                           // create), 0 = chosen by size
 };

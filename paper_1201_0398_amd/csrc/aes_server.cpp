@@ -286,6 +286,7 @@ int launch_slot(aesgpu_server *s, Slot &slot, bool backlog) {
             a.n_bytes = r.n;
             a.rk = reinterpret_cast<const RoundKeys *>(
                 s->h_sched.data() + size_t(r.key) * kSchedWords + (dec ? 64 : 0));
+            a.bpl = s->ctx->blocks_per_lane;
             const int st = launch(s->ctx->d_tables, s->ctx->n_cu, a, slot.stream);
             if (st != AESGPU_OK) return st;
         }

@@ -1,6 +1,8 @@
 """GPU parity of the single-buffer calls (ECB both ways, CTR, the paper's
 LE-128 CTR, CBC decryption) against the CPU oracle, at sizes that span several
-tiles and a ragged tail, plus the edge cases and argument errors."""
+tiles and a ragged tail, plus the edge cases and argument errors; every test
+runs with the blocks per lane chosen by size and with each of 1, 2 and 4
+forced."""
 import hashlib
 import json
 import os
@@ -14,7 +16,7 @@ from gpu_common import from_dev, log, requires_gpu, to_dev
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
 GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "oracle_digests.json")
-TILE = 1024 * 4          # blocks per workgroup step at the default 4 blocks per lane
+TILE = 1024 * 4          # blocks per workgroup step at 4 blocks per lane
 # Sizes in blocks: tiny, wave and workgroup edges, tile edges, and one size that
 # makes every workgroup of a 256-CU grid stride twice with a ragged end.
 SIZES = [1, 2, 63, 64, 65, 1023, 1024, 1025, TILE - 1, TILE, TILE + 1, 3 * TILE + 77]
@@ -27,9 +29,22 @@ def A():
     return aesgpu
 
 
-@pytest.fixture(scope="module")
-def ctx(A):
-    c = A.aesgpu_create()
+@pytest.fixture(scope="module", params=[0, 1, 2, 4], ids=["bpl-auto", "bpl1", "bpl2", "bpl4"])
+def ctx(A, request):
+    """A context per blocks-per-lane setting: chosen by size (auto), or fixed
+    to each kernel variant with AESGPU_FORCE_BPL (read at context creation),
+    so that every test runs each variant."""
+    import os
+    old = os.environ.pop("AESGPU_FORCE_BPL", None)
+    if request.param:
+        os.environ["AESGPU_FORCE_BPL"] = str(request.param)
+    try:
+        c = A.aesgpu_create()
+    finally:
+        os.environ.pop("AESGPU_FORCE_BPL", None)
+        if old is not None:
+            os.environ["AESGPU_FORCE_BPL"] = old
+    log(f"context with blocks per lane {request.param or 'chosen by size'}")
     yield c
     A.aesgpu_destroy(c)
 
