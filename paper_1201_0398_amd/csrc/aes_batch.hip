@@ -1315,8 +1315,11 @@ int aesgpu_batch_run_noalloc(aesgpu_ctx *ctx, const aesgpu_msg *msgs, size_t m,
     const size_t o_cl = o_dummy + 256;
     const size_t total = o_cl + cbc_list.size() * sizeof(uint32_t);
     if (total > AESGPU_NOALLOC_SCRATCH_BYTES) return AESGPU_ESCRATCH;
-    staging.assign(total, 0);
+    // The queue counters must start at zero; the padding between parts is
+    // never read.
+    staging.resize(total);
     uint8_t *h = staging.data();
+    std::memset(h, 0, kCounterBytes);
     if (m) std::memcpy(h + o_msgs, dm.data(), m * sizeof(DevMsg));
     if (!tiles[0].empty()) std::memcpy(h + o_t0, tiles[0].data(), tiles[0].size() * sizeof(Tile));
     if (!tiles[1].empty()) std::memcpy(h + o_t1, tiles[1].data(), tiles[1].size() * sizeof(Tile));
