@@ -199,10 +199,77 @@ __device__ __forceinline__ void tile_store16(rsrc_t r, uint32_t offset, const ui
     __builtin_amdgcn_raw_buffer_store_b128(x, r, offset, 0, kPolicy);
 }
 
+// The rounds of one step: NB blocks per lane, block j of this lane at tile
+// offset step_off + 64 j + lane (base is the same offset from the message's
+// block 0), then the mode's output XOR and the store.
+template <bool kInv, int NB, int kPolicy>
+__device__ __forceinline__ void crypt_step(const uint32_t *lds, const Bases &b, uint32_t kreg,
+                                           uint32_t nr, bool ctr, const CtrConsts &cc,
+                                           const DevMsg &m, uint32_t cbc_mask, uint64_t base,
+                                           uint32_t step_off, uint32_t lane, const uint4 (&d)[NB],
+                                           const uint4 (&prev)[NB], rsrc_t rout) {
+    uint32_t s[NB][4];
+    uint32_t rk[4];
+    round_key(kreg, 0, rk);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const uint64_t idx = base + uint64_t(j) * 64u + lane;
+        if (ctr) {
+            counter_round1(lds, b, cc, m.ctr0 + uint32_t(idx), s[j]);
+        } else {
+            s[j][0] = d[j].x ^ rk[0];
+            s[j][1] = d[j].y ^ rk[1];
+            s[j][2] = d[j].z ^ rk[2];
+            s[j][3] = d[j].w ^ rk[3];
+        }
+    }
+    if (!ctr) {
+        round_key(kreg, 1, rk);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
+    }
+#pragma unroll 1
+    for (uint32_t r = 2; r < nr; ++r) {
+        round_key(kreg, r, rk);
+#pragma unroll
+        for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
+    }
+    round_key(kreg, nr, rk);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        if constexpr (kInv)
+            last_round_inv(lds, b, s[j], rk);
+        else
+            last_round_fwd(lds, b, s[j], rk);
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        uint4 o = make_uint4(s[j][0], s[j][1], s[j][2], s[j][3]);
+        if (ctr) {
+            o.x ^= d[j].x;
+            o.y ^= d[j].y;
+            o.z ^= d[j].z;
+            o.w ^= d[j].w;
+        }
+        if constexpr (kInv) {
+            const bool b0 = base + uint64_t(j) * 64u + lane == 0;
+            o.x ^= (b0 ? m.nonce[0] : prev[j].x) & cbc_mask;
+            o.y ^= (b0 ? m.nonce[1] : prev[j].y) & cbc_mask;
+            o.z ^= (b0 ? m.nonce[2] : prev[j].z) & cbc_mask;
+            o.w ^= (b0 ? m.ctr0 : prev[j].w) & cbc_mask;
+        }
+        tile_store16<kPolicy>(rout, (step_off + uint32_t(j) * 64u + lane) * 16u, o);
+    }
+}
+
 // One tile: nr rounds on BPL blocks per lane per step.  The round loop is not
 // unrolled and takes nr at run time: one short loop body serves all key
 // sizes, so the code a workgroup runs fits the instruction cache even when
-// each CU executes it only once (small batches).
+// each CU executes it only once (small batches).  Whole steps of 64 * BPL
+// blocks run with the next step's blocks loaded ahead; the blocks after the
+// last whole step run 64 at a time, one per lane, so a short tile or a
+// tile's ragged end costs rounds only for the waves' 64-block groups that
+// hold blocks.
 template <bool kInv, int BPL, int kPolicy = 0>
 __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, const BatchParams &p,
                                          const DevMsg &m, const Tile &tile) {
@@ -249,13 +316,19 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     const uint64_t end = first + tile.n_blocks;
     constexpr uint32_t kStep = 64u * BPL;
     const uint64_t lim = end < m.n_full ? end : m.n_full;  // whole blocks of this tile
+    // Sizes of buffer resources are read back as wave-uniform values, so that
+    // the resources stay in SGPRs.
+    const uint32_t n_blk = uniform(lim > first ? uint32_t(lim - first) : 0u);
+    // Blocks in whole steps (all of them at one block per lane).
+    const uint32_t n_main = BPL > 1 ? n_blk - n_blk % kStep : n_blk;
     // Buffer resources over the tile's whole blocks: loads past them read
     // zero and stores past them are dropped, so no lane branches and the
     // compiler can wait for exactly the older loads (the next step's blocks
-    // are loaded while the current step is computed).
-    const uint32_t bytes = lim > first ? 16u * uint32_t(lim - first) : 0u;
-    const rsrc_t rin = buffer_rsrc(in + first, bytes);
-    const rsrc_t rout = buffer_rsrc(out + first, bytes);
+    // are loaded while the current step is computed).  The whole-step loop
+    // loads through resources that end at its last step, so its look-ahead
+    // past that step reads nothing.
+    const rsrc_t rin = buffer_rsrc(in + first, 16u * n_main);
+    const rsrc_t rout = buffer_rsrc(out + first, 16u * n_blk);
     // CBC decryption (Eq. (2)): every block is XORed with the ciphertext
     // block before it (the IV for block 0), read through a resource that
     // starts one block before the tile.  ECB-decrypt tiles issue the same
@@ -263,8 +336,8 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     const bool cbc = kInv && m.mode == AESGPU_MODE_CBC;
     const uint64_t pbase = first > 0 ? first - 1 : 0;
     const uint32_t pshift = first > 0 ? 0u : 1u;  // block 0 has no predecessor
-    const rsrc_t rprev = buffer_rsrc(in + pbase, cbc && lim > first ? 16u * uint32_t(lim - pbase)
-                                                                    : 0u);
+    const rsrc_t rprev =
+        buffer_rsrc(in + pbase, uniform(cbc && n_main ? 16u * (n_main + 1u - pshift) : 0u));
     const uint32_t cbc_mask = cbc ? ~0u : 0u;
     uint4 next[BPL], next_prev[BPL];
 #pragma unroll
@@ -284,15 +357,11 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
         for (int j = 0; j < BPL; ++j)
             tile_store16<kPolicy>(none, (uint32_t(j) * 64u + lane) * 16u, make_uint4(0, 0, 0, 0));
     }
-    for (uint64_t base = first; base < lim; base += kStep) {
+    for (uint32_t step_off = 0; step_off < n_main; step_off += kStep) {
         // Keep the round-key reads inside the loop: hoisting all of them would
         // need 4 * (nr + 1) SGPRs at once.
         asm volatile("" : "+v"(kreg));
-        const uint32_t step_off = uint32_t(base - first);
-        uint32_t s[BPL][4];
         uint4 d[BPL], prev[BPL];
-        uint32_t rk[4];
-        round_key(kreg, 0, rk);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             d[j] = next[j];
@@ -306,54 +375,24 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                     rprev, (step_off + kStep + uint32_t(j) * 64u + lane - pshift) * 16u);
             }
         }
-#pragma unroll
-        for (int j = 0; j < BPL; ++j) {
-            const uint64_t idx = base + uint64_t(j) * 64u + lane;
-            if (ctr) {
-                counter_round1(lds, b, cc, m.ctr0 + uint32_t(idx), s[j]);
-            } else {
-                s[j][0] = d[j].x ^ rk[0];
-                s[j][1] = d[j].y ^ rk[1];
-                s[j][2] = d[j].z ^ rk[2];
-                s[j][3] = d[j].w ^ rk[3];
+        crypt_step<kInv, BPL, kPolicy>(lds, b, kreg, nr, ctr, cc, m, cbc_mask, first + step_off,
+                                       step_off, lane, d, prev, rout);
+    }
+    if constexpr (BPL > 1) {
+        if (n_main < n_blk) {
+            const rsrc_t rin_all = buffer_rsrc(in + first, 16u * n_blk);
+            const rsrc_t rprev_all =
+                buffer_rsrc(in + pbase, uniform(cbc ? 16u * (n_blk + 1u - pshift) : 0u));
+            for (uint32_t step_off = n_main; step_off < n_blk; step_off += 64u) {
+                asm volatile("" : "+v"(kreg));
+                uint4 d[1], prev[1];
+                d[0] = tile_load16<kPolicy>(rin_all, (step_off + lane) * 16u);
+                prev[0] = make_uint4(0, 0, 0, 0);
+                if constexpr (kInv)
+                    prev[0] = tile_load16<kPolicy>(rprev_all, (step_off + lane - pshift) * 16u);
+                crypt_step<kInv, 1, kPolicy>(lds, b, kreg, nr, ctr, cc, m, cbc_mask,
+                                             first + step_off, step_off, lane, d, prev, rout);
             }
-        }
-        if (!ctr) {
-            round_key(kreg, 1, rk);
-#pragma unroll
-            for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], rk);
-        }
-#pragma unroll 1
-        for (uint32_t r = 2; r < nr; ++r) {
-            round_key(kreg, r, rk);
-#pragma unroll
-            for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], rk);
-        }
-        round_key(kreg, nr, rk);
-#pragma unroll
-        for (int j = 0; j < BPL; ++j) {
-            if constexpr (kInv)
-                last_round_inv(lds, b, s[j], rk);
-            else
-                last_round_fwd(lds, b, s[j], rk);
-        }
-#pragma unroll
-        for (int j = 0; j < BPL; ++j) {
-            uint4 o = make_uint4(s[j][0], s[j][1], s[j][2], s[j][3]);
-            if (ctr) {
-                o.x ^= d[j].x;
-                o.y ^= d[j].y;
-                o.z ^= d[j].z;
-                o.w ^= d[j].w;
-            }
-            if constexpr (kInv) {
-                const bool b0 = base + uint64_t(j) * 64u + lane == 0;
-                o.x ^= (b0 ? m.nonce[0] : prev[j].x) & cbc_mask;
-                o.y ^= (b0 ? m.nonce[1] : prev[j].y) & cbc_mask;
-                o.z ^= (b0 ? m.nonce[2] : prev[j].z) & cbc_mask;
-                o.w ^= (b0 ? m.ctr0 : prev[j].w) & cbc_mask;
-            }
-            tile_store16<kPolicy>(rout, (step_off + uint32_t(j) * 64u + lane) * 16u, o);
         }
     }
     if constexpr (!kInv) {
