@@ -84,7 +84,10 @@ __device__ __forceinline__ uint32_t table_u(const uint32_t *lds, int t, uint32_t
 template <bool kInv, int NR>
 __device__ __forceinline__ uint32_t expand_key(const uint32_t *lds, const uint32_t *key) {
     constexpr int nk = NR - 6;
-    const uint32_t lane = threadIdx.x & 63u;
+    // The lane index is re-read here: otherwise the compiler keeps the 60
+    // lane comparisons below as masks through the whole launch.
+    uint32_t lane = threadIdx.x & 63u;
+    asm volatile("" : "+v"(lane));
     uint32_t win[8];  // win[i % nk] = word i
     uint32_t kreg = 0;
 #pragma unroll
@@ -641,11 +644,15 @@ __global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
         __syncthreads();
         if (!__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) continue;
         const uint32_t start = (pass == 0 && my_static < p.n_tiles[set]) ? my_static : kNone;
+        // The staging's addresses are recomputed here rather than kept in
+        // registers through the whole launch.
+        const uint32_t *tables = p.tables;
+        asm volatile("" : "+s"(tables));
         if (set == 0) {
-            stage_tables<false>(lds, p.tables);
+            stage_tables<false>(lds, tables);
             drain_queue<false, BPL>(lds, b, p, start);
         } else {
-            stage_tables<true>(lds, p.tables);
+            stage_tables<true>(lds, tables);
             drain_queue<true, BPL>(lds, b, p, start);
         }
     }
