@@ -106,6 +106,32 @@ def test_mixed_batch_with_cbc(A, ctx, bpl, graph):
     _run_and_check(A, ctx, b, blocks_per_lane=bpl, tile_blocks=128 * bpl, flags=flags)
 
 
+@pytest.mark.parametrize("bpl,tile", [(2, 256), (4, 512), (4, 8192)])
+def test_ragged_tile_ends_every_mode(A, ctx, bpl, tile):
+    """Message lengths at and around multiples of a step (64 blocks per lane
+    slot times blocks per lane) and of the tile, in every mode and direction:
+    the whole steps, the 64-block groups after them and the tile cuts must
+    cover every block once."""
+    rng = np.random.default_rng(9050 + bpl + tile)
+    step = 64 * bpl
+    counts = sorted({1, 63, 64, 65, step - 1, step, step + 1, 2 * step + 63, 3 * step + 64,
+                     tile - 1, tile, tile + 1, tile + step - 1, 2 * tile + 65})
+    kinds = [(0, 0, 0), (0, 1, 0), (2, 1, 0), (2, 0, 0), (1, 0, 0), (1, 0, 9)]  # mode, dir, CTR tail
+    specs = [(c, k) for c in counts for k in kinds]
+    m = len(specs)
+    b = _batch(rng, m, np.array([k[0] for _, k in specs]), max_blocks=1)
+    lengths = np.array([16 * c - (k[2] and 16 - k[2]) for c, k in specs])
+    b["lengths"] = lengths
+    b["dirs"] = np.array([k[1] for _, k in specs])
+    span = 16 * ((lengths + 15) // 16) + 16
+    b["in_off"] = np.concatenate([[0], np.cumsum(span)[:-1]])
+    b["out_off"] = np.concatenate([[0], np.cumsum(span[::-1])[:-1]])[::-1].copy()
+    b["total"] = int(span.sum())
+    b["data"] = rng.integers(0, 256, b["total"], dtype=np.uint8)
+    log(f"case: {m} messages around step {step} and tile {tile}, {b['total']} bytes")
+    _run_and_check(A, ctx, b, blocks_per_lane=bpl, tile_blocks=tile)
+
+
 @pytest.mark.parametrize("m", [1, 15, 16, 17, 65, 1000])
 def test_cbc_only_batches(A, ctx, m):
     """Only CBC messages: encrypt groups of up to 16 per key size (full,
