@@ -27,6 +27,7 @@
 #include <cstring>
 #include <mutex>
 #include <new>
+#include <utility>
 #include <vector>
 
 #include "aes_device.h"
@@ -119,7 +120,10 @@ __device__ __forceinline__ uint32_t expand_key(const uint32_t *lds, const uint32
 template <int NR>
 __device__ __forceinline__ uint32_t decrypt_keys(const uint32_t *lds, const Bases &b,
                                                  uint32_t enc) {
-    const uint32_t i = threadIdx.x & 63u;
+    // The lane index is re-read here, so that the lane-dependent values below
+    // are not kept in registers through the whole launch.
+    uint32_t i = threadIdx.x & 63u;
+    asm volatile("" : "+v"(i));
     const uint32_t src = i < 4 * NR + 4 ? 4 * (NR - i / 4) + (i & 3) : 0;
     const uint32_t w = __builtin_amdgcn_ds_bpermute(int(src * 4), int(enc));
     if (i < 4 || i >= 4 * NR) return w;
@@ -202,12 +206,41 @@ __device__ __forceinline__ void tile_store16(rsrc_t r, uint32_t offset, const ui
     __builtin_amdgcn_raw_buffer_store_b128(x, r, offset, 0, kPolicy);
 }
 
+// k[i] = lane I0 + i of x's row, in every lane (DPP row broadcast).
+template <int I0, int N, int... Is>
+__device__ __forceinline__ void row_words(uint32_t x, uint32_t (&k)[N],
+                                          std::integer_sequence<int, Is...>) {
+    ((k[Is] = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x150 + I0 + Is, 0xf, 0xf, false))),
+     ...);
+}
+
+// Middle rounds at positions Q0 .. Q0 + R - 1 of the 12-round sequence below,
+// NB blocks.  kq[X] holds, in every row of 16 lanes, the 16 round-key words of
+// positions 4X + 1 .. 4X + 4 (lane i: word i % 4 of position 4X + 1 + i / 4);
+// a row broadcast (DPP) gives each key word to all lanes as a VGPR, so the
+// chunk's rounds hold no round key in SGPRs.
+template <bool kInv, int NB, int Q0, int R>
+__device__ __forceinline__ void mid_round_chunk(const uint32_t *lds, const Bases &b,
+                                                const uint32_t (&kq)[3], uint32_t (&s)[NB][4]) {
+    constexpr int kX = (Q0 - 1) / 4;
+    constexpr int kI0 = 4 * (Q0 - 1 - 4 * kX);
+    static_assert(kI0 + 4 * R <= 16, "a chunk stays within one key register");
+    uint32_t k[4 * R];
+    row_words<kI0>(kq[kX], k, std::make_integer_sequence<int, 4 * R>{});
+#pragma unroll
+    for (int t = 0; t < R; ++t) {
+#pragma unroll
+        for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], &k[4 * t]);
+    }
+}
+
 // The rounds of one step: NB blocks per lane, block j of this lane at tile
 // offset step_off + 64 j + lane (base is the same offset from the message's
 // block 0), then the mode's output XOR and the store.
 template <bool kInv, int NB, int kPolicy>
 __device__ __forceinline__ void crypt_step(const uint32_t *lds, const Bases &b, uint32_t kreg,
-                                           uint32_t nr, bool ctr, const CtrConsts &cc,
+                                           const uint32_t (&kq)[3], uint32_t nr, bool ctr,
+                                           const CtrConsts &cc,
                                            const DevMsg &m, uint32_t cbc_mask, uint64_t base,
                                            uint32_t step_off, uint32_t lane, const uint4 (&d)[NB],
                                            const uint4 (&prev)[NB], rsrc_t rout) {
@@ -231,11 +264,31 @@ __device__ __forceinline__ void crypt_step(const uint32_t *lds, const Bases &b, 
 #pragma unroll
         for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
     }
+    if constexpr (NB > 1) {
+        // Rounds 2 .. nr - 1 as one straight sequence of 12 rounds that
+        // AES-192 enters at its third round and AES-128 at its fifth (round
+        // q + nr - 13 at position q), in chunks of two or four rounds whose
+        // round keys come from the per-tile key registers by row broadcast.
+        // Unlike a rolled loop, or round keys read into SGPRs round by round,
+        // this lets the compiler overlap more of the rounds' table reads.
+        switch (nr) {
+            case 14:
+                mid_round_chunk<kInv, NB, 1, 2>(lds, b, kq, s);
+                [[fallthrough]];
+            case 12:
+                mid_round_chunk<kInv, NB, 3, 2>(lds, b, kq, s);
+                [[fallthrough]];
+            default:
+                mid_round_chunk<kInv, NB, 5, 4>(lds, b, kq, s);
+                mid_round_chunk<kInv, NB, 9, 4>(lds, b, kq, s);
+        }
+    } else {
 #pragma unroll 1
-    for (uint32_t r = 2; r < nr; ++r) {
-        round_key(kreg, r, rk);
+        for (uint32_t r = 2; r < nr; ++r) {
+            round_key(kreg, r, rk);
 #pragma unroll
-        for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
+            for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
+        }
     }
     round_key(kreg, nr, rk);
 #pragma unroll
@@ -313,6 +366,14 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     }
 
     const uint32_t lane = threadIdx.x & 63u;
+    // Round keys of the whole steps' middle-round sequence, 16 words per
+    // register and row (lane permutes, once per tile): position q runs round
+    // q + nr - 13, whose word c is lane 4 (q + nr - 13) + c of the schedule.
+    uint32_t kq[3];
+#pragma unroll
+    for (int x = 0; x < 3; ++x)
+        kq[x] = uint32_t(__builtin_amdgcn_ds_bpermute(
+            int((4u * (4u * x + 1u) + (lane & 15u) + 4u * (nr - 13u)) * 4u), int(kreg)));
     const uint4 *in = reinterpret_cast<const uint4 *>(p.in + m.in_off);
     uint4 *out = reinterpret_cast<uint4 *>(p.out + m.out_off);
     const uint64_t first = tile.first_block;
@@ -342,6 +403,49 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     const rsrc_t rprev =
         buffer_rsrc(in + pbase, uniform(cbc && n_main ? 16u * (n_main + 1u - pshift) : 0u));
     const uint32_t cbc_mask = cbc ? ~0u : 0u;
+    // The blocks after the last whole step (64 at a time, one per lane) and
+    // a CTR message's partial last block run first: nothing they need stays
+    // live through the whole steps' rounds, which keeps the SGPRs in use there
+    // few enough for the compiler to keep many table reads in flight.
+    if constexpr (BPL > 1) {
+        if (n_main < n_blk) {
+            const rsrc_t rin_all = buffer_rsrc(in + first, 16u * n_blk);
+            const rsrc_t rprev_all =
+                buffer_rsrc(in + pbase, uniform(cbc ? 16u * (n_blk + 1u - pshift) : 0u));
+            for (uint32_t step_off = n_main; step_off < n_blk; step_off += 64u) {
+                asm volatile("" : "+v"(kreg));
+                uint4 d[1], prev[1];
+                d[0] = tile_load16<kPolicy>(rin_all, (step_off + lane) * 16u);
+                prev[0] = make_uint4(0, 0, 0, 0);
+                if constexpr (kInv)
+                    prev[0] = tile_load16<kPolicy>(rprev_all, (step_off + lane - pshift) * 16u);
+                crypt_step<kInv, 1, kPolicy>(lds, b, kreg, kq, nr, ctr, cc, m, cbc_mask,
+                                             first + step_off, step_off, lane, d, prev, rout);
+            }
+        }
+    }
+    if constexpr (!kInv) {
+        // Partial last block of a CTR message (it lies in the message's last
+        // tile): every lane computes its keystream, lane q < tail writes byte q.
+        if (ctr && m.tail && end > m.n_full) {
+            uint32_t s[4];
+            uint32_t rk[4];
+            counter_round1(lds, b, cc, m.ctr0 + uint32_t(m.n_full), s);
+#pragma unroll 1
+            for (uint32_t r = 2; r < nr; ++r) {
+                round_key(kreg, r, rk);
+                mid_round<false>(lds, b, s, rk);
+            }
+            round_key(kreg, nr, rk);
+            last_round_fwd(lds, b, s, rk);
+            if (lane < m.tail) {
+                const uint8_t *src = reinterpret_cast<const uint8_t *>(in + m.n_full);
+                uint8_t *dst = reinterpret_cast<uint8_t *>(out + m.n_full);
+                const uint32_t w = lane < 4 ? s[0] : lane < 8 ? s[1] : lane < 12 ? s[2] : s[3];
+                dst[lane] = src[lane] ^ uint8_t(w >> (8 * (lane & 3u)));
+            }
+        }
+    }
     uint4 next[BPL], next_prev[BPL];
 #pragma unroll
     for (int j = 0; j < BPL; ++j) next[j] = tile_load16<kPolicy>(rin, (uint32_t(j) * 64u + lane) * 16u);
@@ -378,47 +482,8 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                     rprev, (step_off + kStep + uint32_t(j) * 64u + lane - pshift) * 16u);
             }
         }
-        crypt_step<kInv, BPL, kPolicy>(lds, b, kreg, nr, ctr, cc, m, cbc_mask, first + step_off,
+        crypt_step<kInv, BPL, kPolicy>(lds, b, kreg, kq, nr, ctr, cc, m, cbc_mask, first + step_off,
                                        step_off, lane, d, prev, rout);
-    }
-    if constexpr (BPL > 1) {
-        if (n_main < n_blk) {
-            const rsrc_t rin_all = buffer_rsrc(in + first, 16u * n_blk);
-            const rsrc_t rprev_all =
-                buffer_rsrc(in + pbase, uniform(cbc ? 16u * (n_blk + 1u - pshift) : 0u));
-            for (uint32_t step_off = n_main; step_off < n_blk; step_off += 64u) {
-                asm volatile("" : "+v"(kreg));
-                uint4 d[1], prev[1];
-                d[0] = tile_load16<kPolicy>(rin_all, (step_off + lane) * 16u);
-                prev[0] = make_uint4(0, 0, 0, 0);
-                if constexpr (kInv)
-                    prev[0] = tile_load16<kPolicy>(rprev_all, (step_off + lane - pshift) * 16u);
-                crypt_step<kInv, 1, kPolicy>(lds, b, kreg, nr, ctr, cc, m, cbc_mask,
-                                             first + step_off, step_off, lane, d, prev, rout);
-            }
-        }
-    }
-    if constexpr (!kInv) {
-        // Partial last block of a CTR message (it lies in the message's last
-        // tile): every lane computes its keystream, lane q < tail writes byte q.
-        if (ctr && m.tail && end > m.n_full) {
-            uint32_t s[4];
-            uint32_t rk[4];
-            counter_round1(lds, b, cc, m.ctr0 + uint32_t(m.n_full), s);
-#pragma unroll 1
-            for (uint32_t r = 2; r < nr; ++r) {
-                round_key(kreg, r, rk);
-                mid_round<false>(lds, b, s, rk);
-            }
-            round_key(kreg, nr, rk);
-            last_round_fwd(lds, b, s, rk);
-            if (lane < m.tail) {
-                const uint8_t *src = reinterpret_cast<const uint8_t *>(in + m.n_full);
-                uint8_t *dst = reinterpret_cast<uint8_t *>(out + m.n_full);
-                const uint32_t w = lane < 4 ? s[0] : lane < 8 ? s[1] : lane < 12 ? s[2] : s[3];
-                dst[lane] = src[lane] ^ uint8_t(w >> (8 * (lane & 3u)));
-            }
-        }
     }
 }
 
@@ -580,15 +645,29 @@ __global__ __launch_bounds__(WG) void cbc_encrypt_kernel(BatchParams p, const Ti
 // atomic at all when every tile has a wave of its own.
 constexpr uint32_t kNone = 0xFFFFFFFFu;
 
+// The batch kernel's parameters in its kernel-argument segment (the kernel's
+// only argument, at offset 0), through a pointer the compiler cannot assume
+// constant from one call to the next, so that each call loads afresh.
+__device__ __forceinline__ const BatchParams &kernel_params() {
+    const BatchParams __attribute__((address_space(4))) *k =
+        (const BatchParams __attribute__((address_space(4))) *)__builtin_amdgcn_kernarg_segment_ptr();
+    asm volatile("" : "+s"(k));
+    return *(const BatchParams *)k;
+}
+
 template <bool kInv, int BPL>
-__device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
-                                            const BatchParams &p, uint32_t first) {
+__device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b, uint32_t first) {
     constexpr int set = kInv ? 1 : 0;
-    const DevMsg *__restrict__ msgs = p.msgs;
-    const Tile *__restrict__ tiles = p.tiles[set];
     uint32_t t = first;
     uint32_t run_end = 0;  // end of the run of tiles taken by the last pull
     for (;;) {
+        // The launch's parameters are read again from the kernel-argument
+        // segment for every tile (scalar loads that hit the scalar cache)
+        // rather than held in SGPRs through the tile: with fewer SGPRs in use
+        // the compiler keeps many more table reads in flight in the rounds.
+        const BatchParams &p = kernel_params();
+        const DevMsg *__restrict__ msgs = p.msgs;
+        const Tile *__restrict__ tiles = p.tiles[set];
         t = __builtin_amdgcn_readfirstlane(t);
         if (t == kNone) {
             if (p.n_static[set] >= p.n_tiles[set]) break;  // no dynamic tiles at all
@@ -644,16 +723,17 @@ __global__ __launch_bounds__(kWG) void batch_kernel(BatchParams p) {
         __syncthreads();
         if (!__hip_atomic_load(flag, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT)) continue;
         const uint32_t start = (pass == 0 && my_static < p.n_tiles[set]) ? my_static : kNone;
-        // The staging's addresses are recomputed here rather than kept in
-        // registers through the whole launch.
+        // The staging's indices and addresses are recomputed here rather than
+        // kept in registers through the whole launch.
         const uint32_t *tables = p.tables;
-        asm volatile("" : "+s"(tables));
+        uint32_t tid = threadIdx.x;
+        asm volatile("" : "+s"(tables), "+v"(tid));
         if (set == 0) {
-            stage_tables<false>(lds, tables);
-            drain_queue<false, BPL>(lds, b, p, start);
+            stage_tables_tid<false>(lds, tables, tid);
+            drain_queue<false, BPL>(lds, b, start);
         } else {
-            stage_tables<true>(lds, tables);
-            drain_queue<true, BPL>(lds, b, p, start);
+            stage_tables_tid<true>(lds, tables, tid);
+            drain_queue<true, BPL>(lds, b, start);
         }
     }
     // The last workgroup to finish zeroes the two queue counters (and the

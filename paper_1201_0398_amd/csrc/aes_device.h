@@ -124,12 +124,14 @@ __device__ __forceinline__ void last_round_inv(const uint32_t *lds, const Bases 
     for (int c = 0; c < 4; ++c) s[c] = o[c];
 }
 
-// Copies the table set into the LDS image.  Loads are issued in groups of
-// kGroup before their LDS writes, so the staging costs a few L2 round trips
-// instead of one per word; a wave's loads hit two distinct words (every lane
-// of a wave writes copies of the same table entry).  Needs blockDim.x == WG.
+// Copies the table set into the LDS image; tid is the thread's index in the
+// workgroup.  Loads are issued in groups of kGroup before their LDS writes, so
+// the staging costs a few L2 round trips instead of one per word; a wave's
+// loads hit two distinct words (every lane of a wave writes copies of the same
+// table entry).  Needs blockDim.x == WG.
 template <bool kInv, int WG = kWG, int kGroup = 16>
-__device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ g) {
+__device__ __forceinline__ void stage_tables_tid(uint32_t *lds, const uint32_t *__restrict__ g,
+                                                 uint32_t tid) {
     static_assert(kFwdWords % (WG * kGroup) == 0 && kInvSWords % WG == 0, "workgroup size");
     const uint32_t *src = g + (kInv ? kTd : kTe);
     constexpr int kPer = kFwdWords / WG;
@@ -138,13 +140,13 @@ __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__re
         uint32_t v[kGroup];
 #pragma unroll
         for (int k = 0; k < kGroup; ++k) {
-            const uint32_t i = threadIdx.x + uint32_t(k0 + k) * WG;
+            const uint32_t i = tid + uint32_t(k0 + k) * WG;
             const uint32_t t = ((i >> 14) << 1) | ((i >> 5) & 1u);
             const uint32_t x = (i >> 6) & 0xFFu;
             v[k] = src[t * 256u + x];
         }
 #pragma unroll
-        for (int k = 0; k < kGroup; ++k) lds[threadIdx.x + uint32_t(k0 + k) * WG] = v[k];
+        for (int k = 0; k < kGroup; ++k) lds[tid + uint32_t(k0 + k) * WG] = v[k];
     }
     if constexpr (kInv) {
         constexpr int kPerS = kInvSWords / WG;
@@ -153,13 +155,18 @@ __device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__re
             uint32_t w[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                w[k] = k0 + k < kPerS ? g[kInvSS + ((threadIdx.x + uint32_t(k0 + k) * WG) >> 5)] : 0u;
+                w[k] = k0 + k < kPerS ? g[kInvSS + ((tid + uint32_t(k0 + k) * WG) >> 5)] : 0u;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
-                if (k0 + k < kPerS) lds[kFwdWords + threadIdx.x + uint32_t(k0 + k) * WG] = w[k];
+                if (k0 + k < kPerS) lds[kFwdWords + tid + uint32_t(k0 + k) * WG] = w[k];
         }
     }
     __syncthreads();
+}
+
+template <bool kInv, int WG = kWG, int kGroup = 16>
+__device__ __forceinline__ void stage_tables(uint32_t *lds, const uint32_t *__restrict__ g) {
+    stage_tables_tid<kInv, WG, kGroup>(lds, g, threadIdx.x);
 }
 
 __device__ __forceinline__ uint32_t bswap32(uint32_t v) {
