@@ -210,8 +210,7 @@ __device__ __forceinline__ void tile_store16(rsrc_t r, uint32_t offset, const ui
 template <int I0, int N, int... Is>
 __device__ __forceinline__ void row_words(uint32_t x, uint32_t (&k)[N],
                                           std::integer_sequence<int, Is...>) {
-    ((k[Is] = uint32_t(__builtin_amdgcn_update_dpp(0, int(x), 0x150 + I0 + Is, 0xf, 0xf, false))),
-     ...);
+    ((k[Is] = uint32_t(__builtin_amdgcn_mov_dpp(int(x), 0x150 + I0 + Is, 0xf, 0xf, false))), ...);
 }
 
 // Middle rounds at positions Q0 .. Q0 + R - 1 of the 12-round sequence below,
