@@ -16,11 +16,15 @@
 //   the queue is empty (every wave reaches that exit; no wave waits on
 //   another).  For each tile the wave expands the message key (FIPS-197
 //   KeyExpansion, the key schedule the paper's section 2.1 defers to) with
-//   wave-uniform table reads, so the round keys end up in SGPRs; decryption
-//   keys get InvMixColumns lane-parallel.  The rounds are the single-buffer
-//   kernel's (Eq. (1)); CTR tiles precompute their round-1 constants.
-// * The counter reset and the persistent launches are captured once into a
-//   hipGraph and replayed; the graph is re-captured when the buffers change.
+//   wave-uniform table reads into one register, word i in lane i;
+//   decryption keys get InvMixColumns lane-parallel.  The rounds are the
+//   single-buffer kernel's (Eq. (1)); in whole steps the middle rounds run
+//   as one straight sequence shared by the three key sizes, their round keys
+//   given to every lane by DPP row broadcasts.  CTR tiles precompute their
+//   round-1 constants.
+// * The persistent launches are captured once into a hipGraph and replayed
+//   (the kernel leaves its queue counters at zero); the graph is re-captured
+//   when the buffers change.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
