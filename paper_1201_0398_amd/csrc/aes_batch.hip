@@ -237,6 +237,50 @@ __device__ __forceinline__ void mid_round_chunk(const uint32_t *lds, const Bases
     }
 }
 
+// Copy 0 of T_t[x] (every lane reads the same word: one broadcast read).
+__device__ __forceinline__ uint32_t table_v(const uint32_t *lds, int t, uint32_t x) {
+    return lds_at(lds, uint32_t(t >> 1) * 65536u + (x << 8) + uint32_t(t & 1) * 128u);
+}
+
+// Rounds 1 and 2 of a CTR step whose 64 * NB counters start at ctr_first, a
+// multiple of 64 * NB (block j of this lane has counter ctr_first + 64 j +
+// lane), so they differ only in their low byte.  Round 1 (Eq. (1)): output
+// words 1..3 and three terms of word 0 are the same for the whole step; in
+// round 2 each output word has one term on word 0 (per block) and three on
+// words 1..3 (per step).
+template <int NB>
+__device__ __forceinline__ void ctr_rounds_1_2(const uint32_t *lds, const Bases &b, uint32_t kreg,
+                                               const CtrConsts &cc, uint32_t ctr_first,
+                                               uint32_t lane, uint32_t (&s)[NB][4]) {
+    const uint32_t w3u = bswap32(ctr_first) ^ cc.kvar;
+    const uint32_t u1 = cc.p[1] ^ table_v(lds, 2, (w3u >> 16) & 0xFFu);
+    const uint32_t u2 = cc.p[2] ^ table_v(lds, 1, (w3u >> 8) & 0xFFu);
+    const uint32_t u3 = cc.p[3] ^ table_v(lds, 0, w3u & 0xFFu);
+    uint32_t k2[4];
+    round_key(kreg, 2, k2);
+    const uint32_t c0 = xor3(xor3(table_v(lds, 1, (u1 >> 8) & 0xFFu),
+                                  table_v(lds, 2, (u2 >> 16) & 0xFFu), table_v(lds, 3, u3 >> 24)),
+                             k2[0], 0u);
+    const uint32_t c1 = xor3(xor3(table_v(lds, 0, u1 & 0xFFu), table_v(lds, 1, (u2 >> 8) & 0xFFu),
+                                  table_v(lds, 2, (u3 >> 16) & 0xFFu)),
+                             k2[1], 0u);
+    const uint32_t c2 = xor3(xor3(table_v(lds, 0, u2 & 0xFFu), table_v(lds, 1, (u3 >> 8) & 0xFFu),
+                                  table_v(lds, 3, u1 >> 24)),
+                             k2[2], 0u);
+    const uint32_t c3 = xor3(xor3(table_v(lds, 0, u3 & 0xFFu), table_v(lds, 2, (u1 >> 16) & 0xFFu),
+                                  table_v(lds, 3, u2 >> 24)),
+                             k2[3], 0u);
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+        const uint32_t w3 = bswap32(ctr_first + uint32_t(j) * 64u + lane) ^ cc.kvar;
+        const uint32_t v0 = cc.p[0] ^ tlook<3>(lds, w3, b.t[3]);
+        s[j][0] = tlook<0>(lds, v0, b.t[0]) ^ c0;
+        s[j][1] = tlook<3>(lds, v0, b.t[3]) ^ c1;
+        s[j][2] = tlook<2>(lds, v0, b.t[2]) ^ c2;
+        s[j][3] = tlook<1>(lds, v0, b.t[1]) ^ c3;
+    }
+}
+
 // The rounds of one step: NB blocks per lane, block j of this lane at tile
 // offset step_off + 64 j + lane (base is the same offset from the message's
 // block 0), then the mode's output XOR and the store.
@@ -249,49 +293,78 @@ __device__ __forceinline__ void crypt_step(const uint32_t *lds, const Bases &b, 
                                            const uint4 (&prev)[NB], rsrc_t rout) {
     uint32_t s[NB][4];
     uint32_t rk[4];
-    round_key(kreg, 0, rk);
+    // The rounds up to the last: the standard order, or for whole CTR steps
+    // rounds 1 and 2 with their per-step lookups shared.
+    auto standard_rounds = [&]() {
+        round_key(kreg, 0, rk);
 #pragma unroll
-    for (int j = 0; j < NB; ++j) {
-        const uint64_t idx = base + uint64_t(j) * 64u + lane;
-        if (ctr) {
-            counter_round1(lds, b, cc, m.ctr0 + uint32_t(idx), s[j]);
-        } else {
-            s[j][0] = d[j].x ^ rk[0];
-            s[j][1] = d[j].y ^ rk[1];
-            s[j][2] = d[j].z ^ rk[2];
-            s[j][3] = d[j].w ^ rk[3];
+        for (int j = 0; j < NB; ++j) {
+            const uint64_t idx = base + uint64_t(j) * 64u + lane;
+            if (ctr) {
+                counter_round1(lds, b, cc, m.ctr0 + uint32_t(idx), s[j]);
+            } else {
+                s[j][0] = d[j].x ^ rk[0];
+                s[j][1] = d[j].y ^ rk[1];
+                s[j][2] = d[j].z ^ rk[2];
+                s[j][3] = d[j].w ^ rk[3];
+            }
         }
-    }
-    if (!ctr) {
-        round_key(kreg, 1, rk);
-#pragma unroll
-        for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
-    }
-    if constexpr (NB > 1) {
-        // Rounds 2 .. nr - 1 as one straight sequence of 12 rounds that
-        // AES-192 enters at its third round and AES-128 at its fifth (round
-        // q + nr - 13 at position q), in chunks of two or four rounds whose
-        // round keys come from the per-tile key registers by row broadcast.
-        // Unlike a rolled loop, or round keys read into SGPRs round by round,
-        // this lets the compiler overlap more of the rounds' table reads.
-        switch (nr) {
-            case 14:
-                mid_round_chunk<kInv, NB, 1, 2>(lds, b, kq, s);
-                [[fallthrough]];
-            case 12:
-                mid_round_chunk<kInv, NB, 3, 2>(lds, b, kq, s);
-                [[fallthrough]];
-            default:
-                mid_round_chunk<kInv, NB, 5, 4>(lds, b, kq, s);
-                mid_round_chunk<kInv, NB, 9, 4>(lds, b, kq, s);
-        }
-    } else {
-#pragma unroll 1
-        for (uint32_t r = 2; r < nr; ++r) {
-            round_key(kreg, r, rk);
+        if (!ctr) {
+            round_key(kreg, 1, rk);
 #pragma unroll
             for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
         }
+        if constexpr (NB > 1) {
+            // Rounds 2 .. nr - 1 as one straight sequence of 12 rounds that
+            // AES-192 enters at its third round and AES-128 at its fifth (round
+            // q + nr - 13 at position q), in chunks of two or four rounds whose
+            // round keys come from the per-tile key registers by row broadcast.
+            // Unlike a rolled loop, or round keys read into SGPRs round by round,
+            // this lets the compiler overlap more of the rounds' table reads.
+            switch (nr) {
+                case 14:
+                    mid_round_chunk<kInv, NB, 1, 2>(lds, b, kq, s);
+                    [[fallthrough]];
+                case 12:
+                    mid_round_chunk<kInv, NB, 3, 2>(lds, b, kq, s);
+                    [[fallthrough]];
+                default:
+                    mid_round_chunk<kInv, NB, 5, 4>(lds, b, kq, s);
+                    mid_round_chunk<kInv, NB, 9, 4>(lds, b, kq, s);
+            }
+        } else {
+#pragma unroll 1
+            for (uint32_t r = 2; r < nr; ++r) {
+                round_key(kreg, r, rk);
+#pragma unroll
+                for (int j = 0; j < NB; ++j) mid_round<kInv>(lds, b, s[j], rk);
+            }
+        }
+    };
+    if constexpr (!kInv && NB > 1) {
+        if (ctr) {
+            // A whole CTR step starts at a counter that is a multiple of
+            // 64 * NB (the tile's blocks before the first such counter run
+            // in 64-block groups), so rounds 1 and 2 take 5 table reads per
+            // block and 15 per step, and the sequence enters at round 3.
+            ctr_rounds_1_2<NB>(lds, b, kreg, cc, m.ctr0 + uint32_t(base), lane, s);
+            switch (nr) {
+                case 14:
+                    mid_round_chunk<false, NB, 2, 2>(lds, b, kq, s);
+                    [[fallthrough]];
+                case 12:
+                    mid_round_chunk<false, NB, 4, 1>(lds, b, kq, s);
+                    mid_round_chunk<false, NB, 5, 1>(lds, b, kq, s);
+                    [[fallthrough]];
+                default:
+                    mid_round_chunk<false, NB, 6, 3>(lds, b, kq, s);
+                    mid_round_chunk<false, NB, 9, 4>(lds, b, kq, s);
+            }
+        } else {
+            standard_rounds();
+        }
+    } else {
+        standard_rounds();
     }
     round_key(kreg, nr, rk);
 #pragma unroll
@@ -386,15 +459,23 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     // Sizes of buffer resources are read back as wave-uniform values, so that
     // the resources stay in SGPRs.
     const uint32_t n_blk = uniform(lim > first ? uint32_t(lim - first) : 0u);
-    // Blocks in whole steps (all of them at one block per lane).
-    const uint32_t n_main = BPL > 1 ? n_blk - n_blk % kStep : n_blk;
+    // Tile offsets [h0, h1) run in whole steps (all of them at one block per
+    // lane), the rest 64 blocks at a time.  A CTR tile's whole steps start at
+    // its first block whose counter is a multiple of 64 * BPL.
+    uint32_t h0 = 0;
+    if (BPL > 1 && ctr) {
+        const uint32_t c_first = m.ctr0 + uint32_t(first);
+        const uint32_t head = (kStep - c_first % kStep) % kStep;
+        h0 = uniform(head < n_blk ? head : n_blk);
+    }
+    const uint32_t h1 = BPL > 1 ? h0 + (n_blk - h0) / kStep * kStep : n_blk;
     // Buffer resources over the tile's whole blocks: loads past them read
     // zero and stores past them are dropped, so no lane branches and the
     // compiler can wait for exactly the older loads (the next step's blocks
     // are loaded while the current step is computed).  The whole-step loop
     // loads through resources that end at its last step, so its look-ahead
     // past that step reads nothing.
-    const rsrc_t rin = buffer_rsrc(in + first, 16u * n_main);
+    const rsrc_t rin = buffer_rsrc(in + first, uniform(16u * h1));
     const rsrc_t rout = buffer_rsrc(out + first, 16u * n_blk);
     // CBC decryption (Eq. (2)): every block is XORed with the ciphertext
     // block before it (the IV for block 0), read through a resource that
@@ -404,26 +485,36 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     const uint64_t pbase = first > 0 ? first - 1 : 0;
     const uint32_t pshift = first > 0 ? 0u : 1u;  // block 0 has no predecessor
     const rsrc_t rprev =
-        buffer_rsrc(in + pbase, uniform(cbc && n_main ? 16u * (n_main + 1u - pshift) : 0u));
+        buffer_rsrc(in + pbase, uniform(cbc && h1 ? 16u * (h1 + 1u - pshift) : 0u));
     const uint32_t cbc_mask = cbc ? ~0u : 0u;
-    // The blocks after the last whole step (64 at a time, one per lane) and
-    // a CTR message's partial last block run first: nothing they need stays
+    // The blocks outside the whole steps (64 at a time, one per lane) and a
+    // CTR message's partial last block run first: nothing they need stays
     // live through the whole steps' rounds, which keeps the SGPRs in use there
     // few enough for the compiler to keep many table reads in flight.
     if constexpr (BPL > 1) {
-        if (n_main < n_blk) {
-            const rsrc_t rin_all = buffer_rsrc(in + first, 16u * n_blk);
+        if (h0 > 0 || h1 < n_blk) {
+            const rsrc_t rin_all = buffer_rsrc(in + first, uniform(16u * n_blk));
             const rsrc_t rprev_all =
                 buffer_rsrc(in + pbase, uniform(cbc ? 16u * (n_blk + 1u - pshift) : 0u));
-            for (uint32_t step_off = n_main; step_off < n_blk; step_off += 64u) {
+            // Groups start at 0 while below h0 (their stores end at h0), then
+            // at h1.
+            uint32_t g = h0 > 0 ? 0u : h1;
+            uint32_t stop = h0 > 0 ? h0 : n_blk;
+            while (g < stop) {
                 asm volatile("" : "+v"(kreg));
                 uint4 d[1], prev[1];
-                d[0] = tile_load16<kPolicy>(rin_all, (step_off + lane) * 16u);
+                d[0] = tile_load16<kPolicy>(rin_all, (g + lane) * 16u);
                 prev[0] = make_uint4(0, 0, 0, 0);
                 if constexpr (kInv)
-                    prev[0] = tile_load16<kPolicy>(rprev_all, (step_off + lane - pshift) * 16u);
+                    prev[0] = tile_load16<kPolicy>(rprev_all, (g + lane - pshift) * 16u);
+                const rsrc_t rout_g = buffer_rsrc(out + first, uniform(16u * stop));
                 crypt_step<kInv, 1, kPolicy>(lds, b, kreg, kq, nr, ctr, cc, m, cbc_mask,
-                                             first + step_off, step_off, lane, d, prev, rout);
+                                             first + g, g, lane, d, prev, rout_g);
+                g += 64u;
+                if (g >= stop && stop != n_blk) {
+                    g = h1;
+                    stop = n_blk;
+                }
             }
         }
     }
@@ -451,11 +542,12 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     }
     uint4 next[BPL], next_prev[BPL];
 #pragma unroll
-    for (int j = 0; j < BPL; ++j) next[j] = tile_load16<kPolicy>(rin, (uint32_t(j) * 64u + lane) * 16u);
+    for (int j = 0; j < BPL; ++j)
+        next[j] = tile_load16<kPolicy>(rin, (h0 + uint32_t(j) * 64u + lane) * 16u);
     if constexpr (kInv) {
 #pragma unroll
         for (int j = 0; j < BPL; ++j)
-            next_prev[j] = tile_load16<kPolicy>(rprev, (uint32_t(j) * 64u + lane - pshift) * 16u);
+            next_prev[j] = tile_load16<kPolicy>(rprev, (h0 + uint32_t(j) * 64u + lane - pshift) * 16u);
     }
     {
         // In the loop a step's loads are followed by the previous step's
@@ -467,7 +559,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
         for (int j = 0; j < BPL; ++j)
             tile_store16<kPolicy>(none, (uint32_t(j) * 64u + lane) * 16u, make_uint4(0, 0, 0, 0));
     }
-    for (uint32_t step_off = 0; step_off < n_main; step_off += kStep) {
+    for (uint32_t step_off = h0; step_off < h1; step_off += kStep) {
         // Keep the round-key reads inside the loop: hoisting all of them would
         // need 4 * (nr + 1) SGPRs at once.
         asm volatile("" : "+v"(kreg));
@@ -1116,9 +1208,19 @@ int build_tiles(const aesgpu_msg *msgs, size_t m, uint32_t tile_blocks, std::vec
             tot.cbc_dec_self_overlap = true;
         const int set = inverse ? 1 : 0;
         tot.blocks[set] += n_blocks;
-        for (uint64_t f = 0; f < n_blocks; f += tile_blocks) {
-            const uint64_t n = std::min<uint64_t>(tile_blocks, n_blocks - f);
+        // A CTR message's first tile ends where the counter reaches a multiple
+        // of 256 (when the tile size is one), so that every later tile starts
+        // there: the kernel runs a tile's whole steps from such a counter on
+        // and the blocks before it in 64-block groups.
+        uint64_t first_len = tile_blocks;
+        if (x.mode == AESGPU_MODE_CTR && tile_blocks % 256u == 0) {
+            const uint64_t cut = tile_blocks - (uint64_t(x.ctr0) + tile_blocks) % 256u;
+            if (cut > 0) first_len = cut;
+        }
+        for (uint64_t f = 0; f < n_blocks;) {
+            const uint64_t n = std::min<uint64_t>(f ? tile_blocks : first_len, n_blocks - f);
             tiles[set].push_back(Tile{uint32_t(i), uint32_t(n), f});
+            f += n;
         }
     }
     for (auto &t : tiles)

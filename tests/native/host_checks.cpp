@@ -156,6 +156,10 @@ void check_plan(const std::vector<aesgpu_msg> &msgs, uint32_t tile_blocks) {
             EXPECT(!(g.mode == AESGPU_MODE_CBC && g.dir == AESGPU_DIR_ENCRYPT));
             cover[x.msg].push_back({x.first_block, x.first_block + x.n_blocks});
             blocks[set] += x.n_blocks;
+            // CTR tiles after a message's first start at a counter that is a
+            // multiple of 256 when the tile size is one.
+            if (g.mode == AESGPU_MODE_CTR && tile_blocks % 256 == 0 && x.first_block > 0)
+                EXPECT((uint64_t(g.ctr0) + x.first_block) % 256 == 0);
         }
     }
     EXPECT(blocks[0] == tot.blocks[0] && blocks[1] == tot.blocks[1]);
