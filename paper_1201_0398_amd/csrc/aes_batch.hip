@@ -237,9 +237,11 @@ __device__ __forceinline__ void mid_round_chunk(const uint32_t *lds, const Bases
     }
 }
 
-// Copy 0 of T_t[x] (every lane reads the same word: one broadcast read).
-__device__ __forceinline__ uint32_t table_v(const uint32_t *lds, int t, uint32_t x) {
-    return lds_at(lds, uint32_t(t >> 1) * 65536u + (x << 8) + uint32_t(t & 1) * 128u);
+// T_t[x] from the table image in device memory (te = its forward tables),
+// for an index that is the same in every lane: a scalar load through the
+// scalar cache instead of an LDS read.
+__device__ __forceinline__ uint32_t table_s(const uint32_t *te, int t, uint32_t x) {
+    return as_const(te)[__builtin_amdgcn_readfirstlane(uint32_t(t) * 256u + x)];
 }
 
 // Rounds 1 and 2 of a CTR step whose 64 * NB counters start at ctr_first, a
@@ -247,28 +249,29 @@ __device__ __forceinline__ uint32_t table_v(const uint32_t *lds, int t, uint32_t
 // lane), so they differ only in their low byte.  Round 1 (Eq. (1)): output
 // words 1..3 and three terms of word 0 are the same for the whole step; in
 // round 2 each output word has one term on word 0 (per block) and three on
-// words 1..3 (per step).
+// words 1..3 (per step), read once per step through the scalar cache.
 template <int NB>
-__device__ __forceinline__ void ctr_rounds_1_2(const uint32_t *lds, const Bases &b, uint32_t kreg,
+__device__ __forceinline__ void ctr_rounds_1_2(const uint32_t *lds, const uint32_t *te,
+                                               const Bases &b, uint32_t kreg,
                                                const CtrConsts &cc, uint32_t ctr_first,
                                                uint32_t lane, uint32_t (&s)[NB][4]) {
     const uint32_t w3u = bswap32(ctr_first) ^ cc.kvar;
-    const uint32_t u1 = cc.p[1] ^ table_v(lds, 2, (w3u >> 16) & 0xFFu);
-    const uint32_t u2 = cc.p[2] ^ table_v(lds, 1, (w3u >> 8) & 0xFFu);
-    const uint32_t u3 = cc.p[3] ^ table_v(lds, 0, w3u & 0xFFu);
+    const uint32_t u1 = cc.p[1] ^ table_s(te, 2, (w3u >> 16) & 0xFFu);
+    const uint32_t u2 = cc.p[2] ^ table_s(te, 1, (w3u >> 8) & 0xFFu);
+    const uint32_t u3 = cc.p[3] ^ table_s(te, 0, w3u & 0xFFu);
     uint32_t k2[4];
     round_key(kreg, 2, k2);
-    const uint32_t c0 = xor3(xor3(table_v(lds, 1, (u1 >> 8) & 0xFFu),
-                                  table_v(lds, 2, (u2 >> 16) & 0xFFu), table_v(lds, 3, u3 >> 24)),
+    const uint32_t c0 = xor3(xor3(table_s(te, 1, (u1 >> 8) & 0xFFu),
+                                  table_s(te, 2, (u2 >> 16) & 0xFFu), table_s(te, 3, u3 >> 24)),
                              k2[0], 0u);
-    const uint32_t c1 = xor3(xor3(table_v(lds, 0, u1 & 0xFFu), table_v(lds, 1, (u2 >> 8) & 0xFFu),
-                                  table_v(lds, 2, (u3 >> 16) & 0xFFu)),
+    const uint32_t c1 = xor3(xor3(table_s(te, 0, u1 & 0xFFu), table_s(te, 1, (u2 >> 8) & 0xFFu),
+                                  table_s(te, 2, (u3 >> 16) & 0xFFu)),
                              k2[1], 0u);
-    const uint32_t c2 = xor3(xor3(table_v(lds, 0, u2 & 0xFFu), table_v(lds, 1, (u3 >> 8) & 0xFFu),
-                                  table_v(lds, 3, u1 >> 24)),
+    const uint32_t c2 = xor3(xor3(table_s(te, 0, u2 & 0xFFu), table_s(te, 1, (u3 >> 8) & 0xFFu),
+                                  table_s(te, 3, u1 >> 24)),
                              k2[2], 0u);
-    const uint32_t c3 = xor3(xor3(table_v(lds, 0, u3 & 0xFFu), table_v(lds, 2, (u1 >> 16) & 0xFFu),
-                                  table_v(lds, 3, u2 >> 24)),
+    const uint32_t c3 = xor3(xor3(table_s(te, 0, u3 & 0xFFu), table_s(te, 2, (u1 >> 16) & 0xFFu),
+                                  table_s(te, 3, u2 >> 24)),
                              k2[3], 0u);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
@@ -285,7 +288,8 @@ __device__ __forceinline__ void ctr_rounds_1_2(const uint32_t *lds, const Bases 
 // offset step_off + 64 j + lane (base is the same offset from the message's
 // block 0), then the mode's output XOR and the store.
 template <bool kInv, int NB, int kPolicy>
-__device__ __forceinline__ void crypt_step(const uint32_t *lds, const Bases &b, uint32_t kreg,
+__device__ __forceinline__ void crypt_step(const uint32_t *lds, const uint32_t *te, const Bases &b,
+                                           uint32_t kreg,
                                            const uint32_t (&kq)[3], uint32_t nr, bool ctr,
                                            const CtrConsts &cc,
                                            const DevMsg &m, uint32_t cbc_mask, uint64_t base,
@@ -346,8 +350,9 @@ __device__ __forceinline__ void crypt_step(const uint32_t *lds, const Bases &b, 
             // A whole CTR step starts at a counter that is a multiple of
             // 64 * NB (the tile's blocks before the first such counter run
             // in 64-block groups), so rounds 1 and 2 take 5 table reads per
-            // block and 15 per step, and the sequence enters at round 3.
-            ctr_rounds_1_2<NB>(lds, b, kreg, cc, m.ctr0 + uint32_t(base), lane, s);
+            // block and 15 scalar loads per step, and the sequence enters at
+            // round 3.
+            ctr_rounds_1_2<NB>(lds, te, b, kreg, cc, m.ctr0 + uint32_t(base), lane, s);
             switch (nr) {
                 case 14:
                     mid_round_chunk<false, NB, 2, 2>(lds, b, kq, s);
@@ -445,6 +450,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     // Round keys of the whole steps' middle-round sequence, 16 words per
     // register and row (lane permutes, once per tile): position q runs round
     // q + nr - 13, whose word c is lane 4 (q + nr - 13) + c of the schedule.
+    const uint32_t *te = p.tables + kTe;   // forward tables in device memory
     uint32_t kq[3];
 #pragma unroll
     for (int x = 0; x < 3; ++x)
@@ -508,7 +514,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                 if constexpr (kInv)
                     prev[0] = tile_load16<kPolicy>(rprev_all, (g + lane - pshift) * 16u);
                 const rsrc_t rout_g = buffer_rsrc(out + first, uniform(16u * stop));
-                crypt_step<kInv, 1, kPolicy>(lds, b, kreg, kq, nr, ctr, cc, m, cbc_mask,
+                crypt_step<kInv, 1, kPolicy>(lds, te, b, kreg, kq, nr, ctr, cc, m, cbc_mask,
                                              first + g, g, lane, d, prev, rout_g);
                 g += 64u;
                 if (g >= stop && stop != n_blk) {
@@ -577,7 +583,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
                     rprev, (step_off + kStep + uint32_t(j) * 64u + lane - pshift) * 16u);
             }
         }
-        crypt_step<kInv, BPL, kPolicy>(lds, b, kreg, kq, nr, ctr, cc, m, cbc_mask, first + step_off,
+        crypt_step<kInv, BPL, kPolicy>(lds, te, b, kreg, kq, nr, ctr, cc, m, cbc_mask, first + step_off,
                                        step_off, lane, d, prev, rout);
     }
 }
