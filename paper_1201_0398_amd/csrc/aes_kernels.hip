@@ -154,6 +154,26 @@ __device__ __forceinline__ void counter_state(const Params &p, uint64_t idx, uin
     }
 }
 
+template <int I>
+__device__ __forceinline__ uint32_t row_word(uint32_t x) {
+    return uint32_t(__builtin_amdgcn_mov_dpp(int(x), 0x150 + I, 0xf, 0xf, false));
+}
+
+// Middle rounds R .. NR - 1, round keys from kq by row broadcast: kq[x], lane
+// i of every row, holds word i % 4 of round 4x + 1 + i / 4.
+template <bool kInv, int BPL, int R, int NR>
+__device__ __forceinline__ void rounds_v(const uint32_t *lds, const Bases &b, uint32_t (&s)[BPL][4],
+                                         const uint32_t (&kq)[4]) {
+    if constexpr (R < NR) {
+        constexpr int kX = (R - 1) / 4, kI = 4 * ((R - 1) % 4);
+        const uint32_t k[4] = {row_word<kI>(kq[kX]), row_word<kI + 1>(kq[kX]),
+                               row_word<kI + 2>(kq[kX]), row_word<kI + 3>(kq[kX])};
+#pragma unroll
+        for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], k);
+        rounds_v<kInv, BPL, R + 1, NR>(lds, b, s, kq);
+    }
+}
+
 template <Op OP, int NR, int BPL>
 __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
@@ -189,6 +209,27 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     // tile: they end here (the staging barrier was the last one).
     if (wave_first * BPL >= p.tile) return;
     const Bases b = lane_bases();
+    // AES-256, and AES-192 CTR, take their middle rounds' keys from VGPRs by
+    // row broadcast (DPP) rather than holding all of them in SGPRs: with the
+    // SGPRs near their limit the compiler keeps only 3-4 table reads in
+    // flight per wave (about 16 otherwise), and these kernels ran 6-8% slower.
+    // kq[x], lane i of every row of 16, holds word i % 4 of round 4x + 1 + i / 4.
+    constexpr bool kKeysV = NR == 14 || (kCtr && NR == 12);
+    uint32_t kq[4] = {0, 0, 0, 0};
+    if constexpr (kKeysV) {
+        const uint32_t l15 = threadIdx.x & 15u;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int w = 4 * (4 * x + 1) + i;
+                if (w < 4 * (NR + 1)) v = l15 == uint32_t(i) ? p.rk.w[w] : v;
+            }
+            kq[x] = v;
+            asm volatile("" : "+v"(kq[x]));   // a VGPR value from here on
+        }
+    }
     // In the loop a tile's loads are followed by the previous tile's stores,
     // and the loop top waits for the loads only.  These stores have an empty
     // range and write nothing; they give the loop entry the same order, so
@@ -282,9 +323,12 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
 #pragma unroll
         for (int r = 1; r < NR; ++r) {
             if (r < first) continue;
+            if constexpr (!kKeysV) {
 #pragma unroll
-            for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], &p.rk.w[4 * r]);
+                for (int j = 0; j < BPL; ++j) mid_round<kInv>(lds, b, s[j], &p.rk.w[4 * r]);
+            }
         }
+        if constexpr (kKeysV) rounds_v<kInv, BPL, (kCtr ? 3 : 1), NR>(lds, b, s, kq);
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             if (kInv)
