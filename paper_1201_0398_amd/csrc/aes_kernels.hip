@@ -201,20 +201,29 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     uint4 next_prev = make_uint4(0, 0, 0, 0);   // CBC only
     TileView view = tile_view(p.in, p.out, uint64_t(blockIdx.x) * tile, p.n_full, p.voff, tile);
     load_tile<kLM, BPL>(next, view);
-    if constexpr (OP == Op::kCbcDec)
+    if constexpr (OP == Op::kCbcDec) {
         next_prev = load_wave_prev<BPL>(p.in, uint64_t(blockIdx.x) * tile, wave_first, p.n_full,
                                         uint32_t(tile));
+        // Block 0 is the first block of wave 0's first tile in workgroup 0,
+        // and no later tile holds it: its predecessor, the IV, is put in here
+        // rather than chosen in the loop.  (Four more SGPRs live through the
+        // loop, next to the round keys, made the compiler keep only ≈5 table
+        // reads in flight per wave instead of ≈17.)
+        if (blockIdx.x == 0 && wave_first == 0)
+            next_prev = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
+    }
     stage_tables<kInv>(lds, p.tables);
     // A small tile leaves the workgroup's last waves without blocks in every
     // tile: they end here (the staging barrier was the last one).
     if (wave_first * BPL >= p.tile) return;
     const Bases b = lane_bases();
-    // AES-256, and AES-192 CTR, take their middle rounds' keys from VGPRs by
-    // row broadcast (DPP) rather than holding all of them in SGPRs: with the
-    // SGPRs near their limit the compiler keeps only 3-4 table reads in
-    // flight per wave (about 16 otherwise), and these kernels ran 6-8% slower.
-    // kq[x], lane i of every row of 16, holds word i % 4 of round 4x + 1 + i / 4.
-    constexpr bool kKeysV = NR == 14 || (kCtr && NR == 12);
+    // AES-256, and AES-192 CTR and CBC, take their middle rounds' keys from
+    // VGPRs by row broadcast (DPP) rather than holding all of them in SGPRs:
+    // with the SGPRs near their limit the compiler keeps only 3-4 table reads
+    // in flight per wave (about 16 otherwise), and these kernels ran 6-8%
+    // slower.  kq[x], lane i of every row of 16, holds word i % 4 of round
+    // 4x + 1 + i / 4.
+    constexpr bool kKeysV = NR == 14 || ((kCtr || OP == Op::kCbcDec) && NR == 12);
     uint32_t kq[4] = {0, 0, 0, 0};
     if constexpr (kKeysV) {
         const uint32_t l15 = threadIdx.x & 15u;
@@ -348,19 +357,17 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 // Eq. (2): XOR with the previous ciphertext block.  Slot j > 0
                 // takes the lane's own slot j - 1; slot 0 takes the last slot
                 // of lane L - 1 (a DPP shift of the wave), and lane 0 the
-                // block loaded with the tile (the IV for block 0).
+                // block loaded with the tile (the IV for block 0, set before
+                // the loop).
                 uint4 q;
                 if (j > 0) {
                     q = in[j - 1];
                 } else {
-                    const uint4 prev0 = base + wave_first * BPL == 0
-                                            ? make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3])
-                                            : wave_prev;
                     const uint4 &l = in[BPL - 1];
-                    q.x = __builtin_amdgcn_update_dpp(prev0.x, l.x, 0x138, 0xf, 0xf, false);
-                    q.y = __builtin_amdgcn_update_dpp(prev0.y, l.y, 0x138, 0xf, 0xf, false);
-                    q.z = __builtin_amdgcn_update_dpp(prev0.z, l.z, 0x138, 0xf, 0xf, false);
-                    q.w = __builtin_amdgcn_update_dpp(prev0.w, l.w, 0x138, 0xf, 0xf, false);
+                    q.x = __builtin_amdgcn_update_dpp(wave_prev.x, l.x, 0x138, 0xf, 0xf, false);
+                    q.y = __builtin_amdgcn_update_dpp(wave_prev.y, l.y, 0x138, 0xf, 0xf, false);
+                    q.z = __builtin_amdgcn_update_dpp(wave_prev.z, l.z, 0x138, 0xf, 0xf, false);
+                    q.w = __builtin_amdgcn_update_dpp(wave_prev.w, l.w, 0x138, 0xf, 0xf, false);
                 }
                 o.x ^= q.x;
                 o.y ^= q.y;
