@@ -14,11 +14,13 @@
 //    bits 8..15, the lane's per-table base supplies bits 0..7 and 16..23.
 //  * Decryption adds InvS (replicated into all four bytes of a word) at
 //    131072 + x * 128 + 4c, 32 KiB, for the last round: 160 KiB in total.
-//  * Round keys are kernel arguments, so they are loaded once into SGPRs.
-//  * CTR (32-bit big-endian counter): lane L of a tile holds blocks
-//    L * BPL .. L * BPL + BPL - 1 (lane-major), and the mapping is shifted by
-//    ctr0 mod (64 * BPL) so that every wave holds 64 * BPL <= 256 consecutive
-//    counters starting at a multiple of 64 * BPL.  Then only the low byte of
+//  * Round keys are kernel arguments, so they are loaded once into SGPRs
+//    (AES-256, AES-192 CTR and CBC: the middle rounds' keys from VGPRs).
+//  * CTR (32-bit big-endian counter): wave w of a tile holds the 64 * BPL
+//    consecutive blocks from 64 * BPL * w (slot j of lane L: block
+//    64 * BPL * w + 64 * j + L), and the mapping is shifted by ctr0 mod
+//    (64 * BPL) so that every wave holds 64 * BPL <= 256 consecutive counters
+//    starting at a multiple of 64 * BPL.  Then only the low byte of
 //    the counter differs across the wave: three of the four round-1 lookups
 //    and twelve of the sixteen round-2 lookups have wave-uniform indices and
 //    are read once per wave and tile through the scalar cache, leaving 5 LDS
@@ -58,19 +60,24 @@ struct Params {
     RoundKeys rk;
 };
 
-// Position of slot j of this lane inside a tile of kWG * BPL blocks: slot-major
-// (each wave instruction touches 64 consecutive blocks) or lane-major (each
-// lane holds BPL consecutive blocks).
-template <bool kLaneMajor, int BPL>
+// Position of slot j of this lane inside a tile of kWG * BPL blocks:
+// slot-major (slot j of the workgroup is kWG consecutive blocks) or wave-major
+// (wave w holds the 64 * BPL consecutive blocks from 64 * BPL * w, its slot j
+// the 64 from 64 * j there).  Either way a wave's load or store instruction
+// covers 64 consecutive blocks, 1 KiB.  (With each lane holding BPL
+// consecutive blocks instead, an instruction touches 32 cache lines rather
+// than 8: AES-128 ECB decryption ran 3% slower so.)
+template <bool kWaveMajor, int BPL>
 __device__ __forceinline__ uint32_t tile_slot(int j) {
-    return kLaneMajor ? threadIdx.x * BPL + uint32_t(j) : uint32_t(j) * kWG + threadIdx.x;
+    return kWaveMajor ? (threadIdx.x & ~63u) * BPL + uint32_t(j) * 64u + (threadIdx.x & 63u)
+                      : uint32_t(j) * kWG + threadIdx.x;
 }
 
 // Block index of slot j of this lane in the tile at virtual position base.
 // Lanes before the first block wrap to huge values and fail every range test.
-template <bool kLaneMajor, int BPL>
+template <bool kWaveMajor, int BPL>
 __device__ __forceinline__ uint64_t block_index(uint64_t base, int j, uint32_t voff) {
-    return base + tile_slot<kLaneMajor, BPL>(j) - voff;
+    return base + tile_slot<kWaveMajor, BPL>(j) - voff;
 }
 
 // Buffer resources for the tile at virtual position base, so that every lane
@@ -93,23 +100,40 @@ __device__ __forceinline__ TileView tile_view(const uint4 *in, uint4 *out, uint6
     return {buffer_rsrc(in + first, bytes), buffer_rsrc(out + first, bytes), shift};
 }
 
-template <bool kLaneMajor, int BPL>
+template <bool kWaveMajor, int BPL>
 __device__ __forceinline__ uint32_t lane_offset(const TileView &v, int j) {
-    return (tile_slot<kLaneMajor, BPL>(j) - v.shift) * 16u;
+    return (tile_slot<kWaveMajor, BPL>(j) - v.shift) * 16u;
 }
 
-template <bool kLaneMajor, int BPL>
+template <bool kWaveMajor, int BPL>
 __device__ __forceinline__ void load_tile(uint4 (&v)[BPL], const TileView &t) {
 #pragma unroll
-    for (int j = 0; j < BPL; ++j) v[j] = buffer_load16(t.in, lane_offset<kLaneMajor, BPL>(t, j));
+    for (int j = 0; j < BPL; ++j) v[j] = buffer_load16(t.in, lane_offset<kWaveMajor, BPL>(t, j));
 }
 
-template <bool kLaneMajor, int BPL>
+template <bool kWaveMajor, int BPL>
 __device__ __forceinline__ void store_block(const TileView &t, int j, const uint4 &o) {
-    buffer_store16(t.out, lane_offset<kLaneMajor, BPL>(t, j), o);
+    buffer_store16(t.out, lane_offset<kWaveMajor, BPL>(t, j), o);
 }
 
-// CBC (lane-major tiles): block first - 1, where first is the wave's first
+// Lane L gets x of lane L - 1 (a DPP shift of the wave); lane 0 keeps lane0.
+__device__ __forceinline__ uint4 from_lane_below(const uint4 &lane0, const uint4 &x) {
+    return make_uint4(__builtin_amdgcn_update_dpp(lane0.x, x.x, 0x138, 0xf, 0xf, false),
+                      __builtin_amdgcn_update_dpp(lane0.y, x.y, 0x138, 0xf, 0xf, false),
+                      __builtin_amdgcn_update_dpp(lane0.z, x.z, 0x138, 0xf, 0xf, false),
+                      __builtin_amdgcn_update_dpp(lane0.w, x.w, 0x138, 0xf, 0xf, false));
+}
+
+// Lane 0 gets x of lane 63 (a DPP rotation of the wave; the other lanes get
+// lane L - 1's, which from_lane_below then replaces).
+__device__ __forceinline__ uint4 from_lane_63(const uint4 &x) {
+    return make_uint4(__builtin_amdgcn_mov_dpp(x.x, 0x13C, 0xf, 0xf, false),
+                      __builtin_amdgcn_mov_dpp(x.y, 0x13C, 0xf, 0xf, false),
+                      __builtin_amdgcn_mov_dpp(x.z, 0x13C, 0xf, 0xf, false),
+                      __builtin_amdgcn_mov_dpp(x.w, 0x13C, 0xf, 0xf, false));
+}
+
+// CBC (wave-major tiles): block first - 1, where first is the wave's first
 // block in the tile at base (the same address in every lane), read through a
 // resource that starts one block before the tile; zero where first == 0 (the
 // caller substitutes the IV) or past the end.
@@ -178,7 +202,7 @@ template <Op OP, int NR, int BPL>
 __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
     constexpr bool kCtr = (OP == Op::kCtrBe32 || OP == Op::kCtrLe128);
-    constexpr bool kLM = kCtr || OP == Op::kCbcDec;   // lane-major tiles
+    constexpr bool kWM = kCtr || OP == Op::kCbcDec;   // wave-major tiles
     __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords];
     // Odd waves issue at a higher priority than even ones (a workgroup's
     // waves go to the CU's four SIMDs in turn, so two SIMDs run high and two
@@ -200,7 +224,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     uint4 next[BPL];
     uint4 next_prev = make_uint4(0, 0, 0, 0);   // CBC only
     TileView view = tile_view(p.in, p.out, uint64_t(blockIdx.x) * tile, p.n_full, p.voff, tile);
-    load_tile<kLM, BPL>(next, view);
+    load_tile<kWM, BPL>(next, view);
     if constexpr (OP == Op::kCbcDec) {
         next_prev = load_wave_prev<BPL>(p.in, uint64_t(blockIdx.x) * tile, wave_first, p.n_full,
                                         uint32_t(tile));
@@ -247,7 +271,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         const rsrc_t none = buffer_rsrc(p.out, 0);
 #pragma unroll
         for (int j = 0; j < BPL; ++j)
-            buffer_store16(none, lane_offset<kLM, BPL>(view, j), make_uint4(0, 0, 0, 0));
+            buffer_store16(none, lane_offset<kWM, BPL>(view, j), make_uint4(0, 0, 0, 0));
     }
     for (uint64_t base = uint64_t(blockIdx.x) * tile; base < v_end; base += stride) {
         uint32_t s[BPL][4];
@@ -257,7 +281,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         const uint4 wave_prev = next_prev;
         const TileView cur = view;
         view = tile_view(p.in, p.out, base + stride, p.n_full, p.voff, tile);
-        load_tile<kLM, BPL>(next, view);
+        load_tile<kWM, BPL>(next, view);
         if constexpr (OP == Op::kCbcDec)
             next_prev = load_wave_prev<BPL>(p.in, base + stride, wave_first, p.n_full,
                                             uint32_t(tile));
@@ -306,7 +330,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
-            const uint64_t idx = block_index<kLM, BPL>(base, j, p.voff);
+            const uint64_t idx = block_index<kWM, BPL>(base, j, p.voff);
             if constexpr (OP == Op::kEcbEnc || OP == Op::kEcbDec || OP == Op::kCbcDec) {
                 s[j][0] = in[j].x ^ p.rk.w[0];
                 s[j][1] = in[j].y ^ p.rk.w[1];
@@ -345,6 +369,14 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
             else
                 last_round_fwd(lds, b, s[j], &p.rk.w[4 * NR]);
         }
+        if constexpr (OP == Op::kCbcDec) {
+            // Keeps the wave shuffles of the ciphertext below (DPP) after the
+            // last round's table reads: placed among the rounds, they held 16
+            // more VGPRs there and the compiler kept fewer reads in flight.
+#pragma unroll
+            for (int j = 0; j < BPL; ++j)
+                asm volatile("" : "+v"(in[j].x), "+v"(in[j].y), "+v"(in[j].z), "+v"(in[j].w));
+        }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
             uint4 o = make_uint4(s[j][0], s[j][1], s[j][2], s[j][3]);
@@ -354,27 +386,18 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 o.z ^= in[j].z;
                 o.w ^= in[j].w;
             } else if constexpr (OP == Op::kCbcDec) {
-                // Eq. (2): XOR with the previous ciphertext block.  Slot j > 0
-                // takes the lane's own slot j - 1; slot 0 takes the last slot
-                // of lane L - 1 (a DPP shift of the wave), and lane 0 the
-                // block loaded with the tile (the IV for block 0, set before
-                // the loop).
-                uint4 q;
-                if (j > 0) {
-                    q = in[j - 1];
-                } else {
-                    const uint4 &l = in[BPL - 1];
-                    q.x = __builtin_amdgcn_update_dpp(wave_prev.x, l.x, 0x138, 0xf, 0xf, false);
-                    q.y = __builtin_amdgcn_update_dpp(wave_prev.y, l.y, 0x138, 0xf, 0xf, false);
-                    q.z = __builtin_amdgcn_update_dpp(wave_prev.z, l.z, 0x138, 0xf, 0xf, false);
-                    q.w = __builtin_amdgcn_update_dpp(wave_prev.w, l.w, 0x138, 0xf, 0xf, false);
-                }
+                // Eq. (2): XOR with the previous ciphertext block: slot j of
+                // lane L - 1; for lane 0, slot j - 1 of lane 63, or for slot 0
+                // the block loaded with the tile (the IV for block 0, set
+                // before the loop).
+                const uint4 q = from_lane_below(j > 0 ? from_lane_63(in[j > 0 ? j - 1 : 0]) : wave_prev,
+                                                in[j]);
                 o.x ^= q.x;
                 o.y ^= q.y;
                 o.z ^= q.z;
                 o.w ^= q.w;
             }
-            store_block<kLM, BPL>(cur, j, o);
+            store_block<kWM, BPL>(cur, j, o);
         }
     }
     if constexpr (kCtr) {
