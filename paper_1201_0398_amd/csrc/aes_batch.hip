@@ -389,11 +389,23 @@ __device__ __forceinline__ void crypt_step(const uint32_t *lds, const uint32_t *
             o.w ^= d[j].w;
         }
         if constexpr (kInv) {
-            const bool b0 = base + uint64_t(j) * 64u + lane == 0;
-            o.x ^= (b0 ? m.nonce[0] : prev[j].x) & cbc_mask;
-            o.y ^= (b0 ? m.nonce[1] : prev[j].y) & cbc_mask;
-            o.z ^= (b0 ? m.nonce[2] : prev[j].z) & cbc_mask;
-            o.w ^= (b0 ? m.ctr0 : prev[j].w) & cbc_mask;
+            // CBC (Eq. (2)): the ciphertext block before, the IV for block 0.
+            // Whole steps find the IV in prev already (run_tile puts it in
+            // before the step loop): choosing it here would keep four more
+            // SGPRs live through the rounds, and with the SGPRs at their
+            // limit the compiler keeps fewer table reads in flight.
+            if constexpr (NB == 1) {
+                const bool b0 = base + uint64_t(j) * 64u + lane == 0;
+                o.x ^= (b0 ? m.nonce[0] : prev[j].x) & cbc_mask;
+                o.y ^= (b0 ? m.nonce[1] : prev[j].y) & cbc_mask;
+                o.z ^= (b0 ? m.nonce[2] : prev[j].z) & cbc_mask;
+                o.w ^= (b0 ? m.ctr0 : prev[j].w) & cbc_mask;
+            } else {
+                o.x ^= prev[j].x & cbc_mask;
+                o.y ^= prev[j].y & cbc_mask;
+                o.z ^= prev[j].z & cbc_mask;
+                o.w ^= prev[j].w & cbc_mask;
+            }
         }
         tile_store16<kPolicy>(rout, (step_off + uint32_t(j) * 64u + lane) * 16u, o);
     }
@@ -554,6 +566,10 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
 #pragma unroll
         for (int j = 0; j < BPL; ++j)
             next_prev[j] = tile_load16<kPolicy>(rprev, (h0 + uint32_t(j) * 64u + lane - pshift) * 16u);
+        // Message block 0 can only be the first whole step's slot 0 of lane
+        // 0 (its predecessor load read nothing): its predecessor is the IV.
+        if (first + h0 == 0 && lane == 0)
+            next_prev[0] = make_uint4(m.nonce[0], m.nonce[1], m.nonce[2], m.ctr0);
     }
     {
         // In the loop a step's loads are followed by the previous step's
