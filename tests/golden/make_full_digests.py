@@ -7,6 +7,8 @@ Workloads (``paper_1201_0398_amd.workloads``):
 
 * 1 GiB, seed 1: ECB encryption and ECB decryption of the random buffer with
   each of the three keys, and AES-128 CTR (nonce || BE32 counter from 1);
+* the same buffer decrypted in CBC mode with the AES-128 and AES-256 keys, IV
+  = the workload's nonce followed by its ctr0 as 4 big-endian bytes;
 * 4 GiB, seed 2: AES-256 CTR from counter 1, in 256 MiB chunks (the counter
   advances by 2^24 per chunk);
 * 65,536 messages, seed 3: the packed output buffer of the encryption run
@@ -57,6 +59,21 @@ def gib1(out: dict) -> None:
     out["gib1_ctr128_sha256"] = sha(oracle.ctr(w.keys[128], w.nonce, w.ctr0, w.data))
 
 
+def cbc_iv(w) -> np.ndarray:
+    """The CBC IV of the 1 GiB workload: its 12-byte nonce, then ctr0 as 4
+    big-endian bytes (a fixed derivation from the seeded inputs)."""
+    return np.concatenate([np.asarray(w.nonce, dtype=np.uint8),
+                           np.frombuffer(int(w.ctr0).to_bytes(4, "big"), dtype=np.uint8)])
+
+
+def gib1_cbc(out: dict) -> None:
+    w = workloads.single_1gib(seed=1)
+    for bits in (128, 256):
+        log(f"1 GiB CBC-{bits} decrypt")
+        out[f"gib1_cbc{bits}_decrypt_sha256"] = sha(oracle.cbc_decrypt(w.keys[bits], cbc_iv(w),
+                                                                       w.data))
+
+
 def gib4(out: dict) -> None:
     w = workloads.ctr_4gib(seed=2)
     out["gib4_input_sha256"] = sha(w.data)
@@ -92,7 +109,7 @@ def batched(out: dict) -> None:
     out["batched_decrypt_sha256"] = sha(dec)
 
 
-PARTS = {"gib1": gib1, "gib4": gib4, "batched": batched}
+PARTS = {"gib1": gib1, "gib1_cbc": gib1_cbc, "gib4": gib4, "batched": batched}
 
 
 def main():

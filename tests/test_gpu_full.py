@@ -5,6 +5,7 @@ oracle's whole output (``golden/full_size_digests.json``, written by
 ``golden/make_full_digests.py`` from the oracle alone; the oracle takes about
 half an hour over these workloads, so it is not re-run here).  The input's
 digest is checked first, so a change in the input recipe shows as such.
+CBC decryption runs on the 1 GiB buffer with the AES-128 and AES-256 keys.
 Sampled blocks are also recomputed by the oracle one by one (both ends,
 random positions, tile and grid-stride edges), to name the first wrong block
 if a digest differs."""
@@ -89,6 +90,28 @@ def test_1gib_ctr128(A, ctx, gib, digests):
     assert sha256_dev(d_out) == digests["gib1_ctr128_sha256"]
     A.aesgpu_ctr_xcrypt(ctx, k, gib.nonce, gib.ctr0, d_out, d_out)
     assert torch.equal(d_out, d_in)
+
+
+@pytest.mark.parametrize("bits", [128, 256])
+def test_1gib_cbc_decrypt(A, ctx, gib, digests, bits):
+    """CBC decryption (Eq. (2)) of the whole 1 GiB buffer; IV = the
+    workload's nonce then ctr0 as 4 big-endian bytes."""
+    import torch
+    log(f"case: 1 GiB CBC-{bits} decrypt, whole buffer")
+    key = gib.keys[bits]
+    k = A.aesgpu_expand_key(key)
+    iv = np.concatenate([np.asarray(gib.nonce, dtype=np.uint8),
+                         np.frombuffer(int(gib.ctr0).to_bytes(4, "big"), dtype=np.uint8)])
+    n = gib.data.size // 16
+    d_in = to_dev(gib.data)
+    d_out = torch.empty_like(d_in)
+    A.aesgpu_cbc_decrypt(ctx, k, iv, d_in, d_out)
+    idx = sample_indices(n, np.random.default_rng(bits + 1), boundaries=[TILE, GRID_STEP])
+    blocks = gib.data.reshape(n, 16)
+    prev = np.where((idx == 0)[:, None], iv[None, :], blocks[np.maximum(idx, 1) - 1])
+    want = oracle.ecb_sampled(key, gib.data, idx, decrypt=True) ^ prev
+    assert np.array_equal(gather_blocks(d_out, idx), want)
+    assert sha256_dev(d_out) == digests[f"gib1_cbc{bits}_decrypt_sha256"]
 
 
 def test_4gib_ctr256(A, ctx, digests):
