@@ -9,6 +9,9 @@ Workloads (``paper_1201_0398_amd.workloads``):
   each of the three keys, and AES-128 CTR (nonce || BE32 counter from 1);
 * the same buffer decrypted in CBC mode with the AES-128 and AES-256 keys, IV
   = the workload's nonce followed by its ctr0 as 4 big-endian bytes;
+* the same buffer through the paper's LE-128 counter mode with the AES-192 key:
+  IV = 2^32 - 2^25 as 4 little-endian bytes (so counter word 0 wraps in the
+  middle of the buffer) followed by the nonce, block index from 0;
 * 4 GiB, seed 2: AES-256 CTR from counter 1, in 256 MiB chunks (the counter
   advances by 2^24 per chunk);
 * 65,536 messages, seed 3: the packed output buffer of the encryption run
@@ -74,6 +77,19 @@ def gib1_cbc(out: dict) -> None:
                                                                        w.data))
 
 
+def le128_iv(w) -> np.ndarray:
+    """The LE-128 CTR IV of the 1 GiB workload: word 0 = 2^32 - 2^25 (it
+    wraps after 2^25 of the buffer's 2^26 blocks), words 1..3 = the nonce."""
+    return np.concatenate([np.frombuffer((2**32 - 2**25).to_bytes(4, "little"), dtype=np.uint8),
+                           np.asarray(w.nonce, dtype=np.uint8)])
+
+
+def gib1_le128(out: dict) -> None:
+    w = workloads.single_1gib(seed=1)
+    log("1 GiB LE-128 CTR-192")
+    out["gib1_ctrle128_192_sha256"] = sha(oracle.ctr_le128(w.keys[192], le128_iv(w), 0, w.data))
+
+
 def gib4(out: dict) -> None:
     w = workloads.ctr_4gib(seed=2)
     out["gib4_input_sha256"] = sha(w.data)
@@ -109,7 +125,8 @@ def batched(out: dict) -> None:
     out["batched_decrypt_sha256"] = sha(dec)
 
 
-PARTS = {"gib1": gib1, "gib1_cbc": gib1_cbc, "gib4": gib4, "batched": batched}
+PARTS = {"gib1": gib1, "gib1_cbc": gib1_cbc, "gib1_le128": gib1_le128, "gib4": gib4,
+         "batched": batched}
 
 
 def main():

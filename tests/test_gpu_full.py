@@ -5,7 +5,8 @@ oracle's whole output (``golden/full_size_digests.json``, written by
 ``golden/make_full_digests.py`` from the oracle alone; the oracle takes about
 half an hour over these workloads, so it is not re-run here).  The input's
 digest is checked first, so a change in the input recipe shows as such.
-CBC decryption runs on the 1 GiB buffer with the AES-128 and AES-256 keys.
+CBC decryption runs on the 1 GiB buffer with the AES-128 and AES-256 keys, the
+paper's LE-128 counter mode with the AES-192 key.
 Sampled blocks are also recomputed by the oracle one by one (both ends,
 random positions, tile and grid-stride edges), to name the first wrong block
 if a digest differs."""
@@ -112,6 +113,26 @@ def test_1gib_cbc_decrypt(A, ctx, gib, digests, bits):
     want = oracle.ecb_sampled(key, gib.data, idx, decrypt=True) ^ prev
     assert np.array_equal(gather_blocks(d_out, idx), want)
     assert sha256_dev(d_out) == digests[f"gib1_cbc{bits}_decrypt_sha256"]
+
+
+def test_1gib_ctr_le128_192(A, ctx, gib, digests):
+    """The paper's LE-128 counter over the whole 1 GiB buffer, AES-192: IV
+    word 0 = 2^32 - 2^25, so counter word 0 wraps halfway and the call is
+    split there; words 1..3 = the workload's nonce."""
+    import torch
+    log("case: 1 GiB LE-128 CTR-192, whole buffer, word 0 wraps halfway")
+    key = gib.keys[192]
+    k = A.aesgpu_expand_key(key)
+    iv = np.concatenate([np.frombuffer((2**32 - 2**25).to_bytes(4, "little"), dtype=np.uint8),
+                         np.asarray(gib.nonce, dtype=np.uint8)])
+    d_in = to_dev(gib.data)
+    d_out = torch.empty_like(d_in)
+    A.aesgpu_ctr_le128_xcrypt(ctx, k, iv, 0, d_in, d_out)
+    n = gib.data.size // 16
+    for lo in (0, (1 << 25) - 2048, n - 2048):
+        want = oracle.ctr_le128(key, iv, lo, gib.data[16 * lo:16 * (lo + 4096)])
+        assert np.array_equal(d_out[16 * lo:16 * (lo + 4096)].cpu().numpy(), want), f"blocks from {lo}"
+    assert sha256_dev(d_out) == digests["gib1_ctrle128_192_sha256"]
 
 
 def test_4gib_ctr256(A, ctx, digests):
