@@ -16,7 +16,10 @@ Workloads (``paper_1201_0398_amd.workloads``):
   advances by 2^24 per chunk);
 * 65,536 messages, seed 3: the packed output buffer of the encryption run
   and of the decryption run (every message decrypted: ECB messages through
-  the inverse cipher, CTR messages through the same keystream).
+  the inverse cipher, CTR messages through the same keystream);
+* 65,536 CBC messages, seed 6 (``workloads.cbc_batch``): the packed output of
+  CBC encryption of every message, and of CBC decryption of the same input
+  bytes taken as ciphertext.
 
 Calls only the oracle and the seeded input generators.  Takes about half an
 hour on 8 cores.  Run from the repository root:
@@ -125,8 +128,26 @@ def batched(out: dict) -> None:
     out["batched_decrypt_sha256"] = sha(dec)
 
 
+def cbc_batch(out: dict) -> None:
+    w = workloads.cbc_batch(seed=6)
+    m = w.lengths.size
+    out["cbc_batch_input_sha256"] = sha(w.data)
+    enc = np.empty_like(w.data)
+    dec = np.empty_like(w.data)
+    t0 = time.time()
+    for j in range(m):
+        o, L = int(w.offsets[j]), int(w.lengths[j])
+        key = w.keys[j, : int(w.key_bits[j]) // 8]
+        enc[o:o + L] = oracle.cbc_encrypt(key, w.ivs[j], w.data[o:o + L])
+        dec[o:o + L] = oracle.cbc_decrypt(key, w.ivs[j], w.data[o:o + L])
+        if j % 16384 == 16383:
+            log(f"CBC batch: {j + 1} of {m} messages ({time.time() - t0:.0f} s)")
+    out["cbc_batch_encrypt_sha256"] = sha(enc)
+    out["cbc_batch_decrypt_sha256"] = sha(dec)
+
+
 PARTS = {"gib1": gib1, "gib1_cbc": gib1_cbc, "gib1_le128": gib1_le128, "gib4": gib4,
-         "batched": batched}
+         "batched": batched, "cbc_batch": cbc_batch}
 
 
 def main():
@@ -138,7 +159,8 @@ def main():
         with open(OUT) as f:
             out = json.load(f)
     out["recipe"] = ("workloads.single_1gib(seed=1), workloads.ctr_4gib(seed=2), "
-                     "workloads.batched(seed=3); digests of whole oracle outputs")
+                     "workloads.batched(seed=3), workloads.cbc_batch(seed=6); "
+                     "digests of whole oracle outputs")
     for name in args.only:
         PARTS[name](out)
         with open(OUT, "w") as f:

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from gpu_common import from_dev, log, requires_gpu, to_dev
+from gpu_common import from_dev, full_size_digests, log, requires_gpu, sha256_dev, to_dev
 
 pytestmark = [pytest.mark.gpu, requires_gpu]
 
@@ -200,6 +200,43 @@ def test_cbc_encrypt_one_long_message_golden(A, ctx):
         assert got == json.load(open(golden))["cbc128_encrypt_sha256"]
     finally:
         A.aesgpu_batch_free(plan)
+
+
+def test_full_cbc_batch_workload(A, ctx):
+    """The 65,536-message CBC workload the benchmark times (seed 6): every
+    output byte of the encryption launch and of the decryption launch (the same
+    input taken as ciphertext) against digests of the oracle's outputs
+    (``golden/full_size_digests.json``), plus the first 64 messages each
+    recomputed by the oracle, to name a wrong message."""
+    import hashlib
+
+    import torch
+    from paper_1201_0398_amd import workloads
+    dg = full_size_digests()
+    w = workloads.cbc_batch(seed=6)
+    assert hashlib.sha256(memoryview(w.data)).hexdigest() == dg["cbc_batch_input_sha256"], \
+        "the CBC batch input recipe changed"
+    m = w.lengths.size
+    d_keys = torch.from_numpy(w.keys.reshape(-1).copy()).to("cuda")
+    d_in = to_dev(w.data)
+    for name, direction in (("encrypt", 0), ("decrypt", 1)):
+        log(f"case: 65,536-message CBC batch, {name}")
+        msgs = A.make_msgs(w.offsets, w.offsets, w.lengths, np.arange(m), w.key_bits,
+                           np.full(m, A.AESGPU_MODE_CBC), np.full(m, direction), iv=w.ivs)
+        plan = A.aesgpu_batch_plan(ctx, msgs)
+        try:
+            d_out = torch.zeros_like(d_in)
+            A.aesgpu_batch_run(plan, d_keys, m, d_in, d_out)
+            torch.cuda.synchronize()
+        finally:
+            A.aesgpu_batch_free(plan)
+        out = from_dev(d_out)
+        f = oracle.cbc_encrypt if direction == 0 else oracle.cbc_decrypt
+        for j in range(64):
+            o, L = int(w.offsets[j]), int(w.lengths[j])
+            key = w.keys[j, : int(w.key_bits[j]) // 8]
+            assert np.array_equal(out[o:o + L], f(key, w.ivs[j], w.data[o:o + L])), f"message {j}"
+        assert sha256_dev(d_out) == dg[f"cbc_batch_{name}_sha256"], f"CBC batch {name}"
 
 
 def test_cbc_plan_validation(A, ctx):
