@@ -230,9 +230,9 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                                         uint32_t(tile));
         // Block 0 is the first block of wave 0's first tile in workgroup 0,
         // and no later tile holds it: its predecessor, the IV, is put in here
-        // rather than chosen in the loop.  (Four more SGPRs live through the
-        // loop, next to the round keys, made the compiler keep only ≈5 table
-        // reads in flight per wave instead of ≈17.)
+        // rather than chosen in the loop.  (Chosen there, it put a branch in
+        // the loop and kept four more SGPRs live, and the compiler kept only
+        // ≈5 table reads in flight per wave instead of ≈17.)
         if (blockIdx.x == 0 && wave_first == 0)
             next_prev = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
     }
