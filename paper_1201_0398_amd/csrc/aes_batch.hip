@@ -419,12 +419,25 @@ __device__ __forceinline__ void crypt_step(const uint32_t *lds, const uint32_t *
 // last whole step run 64 at a time, one per lane, so a short tile or a
 // tile's ragged end costs rounds only for the waves' 64-block groups that
 // hold blocks.
+// A wave's last expanded key schedule (lane i holds word i), with the key
+// slot and round count it was expanded for.
+struct KeyCache {
+    uint32_t slot = 0xFFFFFFFFu;
+    uint32_t nr = 0;
+    uint32_t kreg = 0;
+};
+
 template <bool kInv, int BPL, int kPolicy = 0>
 __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, const BatchParams &p,
-                                         const DevMsg &m, const Tile &tile) {
+                                         const DevMsg &m, const Tile &tile,
+                                         KeyCache *kc = nullptr) {
     const uint32_t nr = m.nr;
     uint32_t kreg;
-    if (p.sched) {
+    if (kc != nullptr && kc->slot == m.key_slot && kc->nr == nr) {
+        // The wave's previous tile had the same key (consecutive tiles of one
+        // message, in the queue's order): no expansion.
+        kreg = kc->kreg;
+    } else if (p.sched) {
         // Resident schedule: lane i loads word i (encryption words first,
         // then the equivalent-inverse-cipher words).
         const uint32_t lane = threadIdx.x & 63u;
@@ -433,6 +446,7 @@ __device__ __forceinline__ void run_tile(const uint32_t *lds, const Bases &b, co
     } else {
         const uint32_t *key = reinterpret_cast<const uint32_t *>(p.keys + 32ull * m.key_slot);
         kreg = schedule_of<kInv>(lds, b, key, nr);
+        if (kc != nullptr) *kc = KeyCache{m.key_slot, nr, kreg};
     }
 
     const bool ctr = !kInv && m.mode == AESGPU_MODE_CTR;
@@ -777,6 +791,7 @@ __device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
     constexpr int set = kInv ? 1 : 0;
     uint32_t t = first;
     uint32_t run_end = 0;  // end of the run of tiles taken by the last pull
+    KeyCache kc;
     for (;;) {
         // The launch's parameters are read again from the kernel-argument
         // segment for every tile (scalar loads that hit the scalar cache)
@@ -802,7 +817,7 @@ __device__ __forceinline__ void drain_queue(const uint32_t *lds, const Bases &b,
         // descriptors during a launch), so every field is uniform.
         const Tile tile = load_uniform(tiles + t);
         const DevMsg m = load_uniform(msgs + tile.msg);
-        run_tile<kInv, BPL>(lds, b, p, m, tile);
+        run_tile<kInv, BPL>(lds, b, p, m, tile, &kc);
         t = t + 1 < run_end ? t + 1 : kNone;
     }
 }
