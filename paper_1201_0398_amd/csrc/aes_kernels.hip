@@ -73,13 +73,6 @@ __device__ __forceinline__ uint32_t tile_slot(int j) {
                       : uint32_t(j) * kWG + threadIdx.x;
 }
 
-// Block index of slot j of this lane in the tile at virtual position base.
-// Lanes before the first block wrap to huge values and fail every range test.
-template <bool kWaveMajor, int BPL>
-__device__ __forceinline__ uint64_t block_index(uint64_t base, int j, uint32_t voff) {
-    return base + tile_slot<kWaveMajor, BPL>(j) - voff;
-}
-
 // Buffer resources for the tile at virtual position base, so that every lane
 // issues its loads and stores without a branch and the compiler can place
 // the waits that let the next tile's loads overlap this tile's rounds.  The
@@ -273,7 +266,12 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         for (int j = 0; j < BPL; ++j)
             buffer_store16(none, lane_offset<kWM, BPL>(view, j), make_uint4(0, 0, 0, 0));
     }
-    for (uint64_t base = uint64_t(blockIdx.x) * tile; base < v_end; base += stride) {
+    // A wave leaves the loop at the first tile that has no block for it
+    // (its first slot is its lowest position in a tile): in a grid-stride
+    // launch the last tiles are often partial, and a partial tile of a few
+    // blocks otherwise costs its workgroup a whole tile's rounds.
+    const uint64_t wave_lo = kWM ? uint64_t(wave_first) * BPL : wave_first;
+    for (uint64_t base = uint64_t(blockIdx.x) * tile; base + wave_lo < v_end; base += stride) {
         uint32_t s[BPL][4];
         uint4 in[BPL];
 #pragma unroll
@@ -295,6 +293,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         uint32_t c[4] = {0, 0, 0, 0};   // round-2 uniform part, per output word
         uint32_t r1 = 0;                // round-1 uniform part of word 0
         uint32_t y0 = 0;                // LE-128: counter word 0 of the wave's first slot
+        uint32_t w3u = 0;               // BE32: whitened word 3 of the wave's first counter
         if constexpr (kCtr) {
             const uint32_t *te = p.tables + kTe;
             uint32_t u1, u2, u3;        // round-1 output words 1..3
@@ -302,7 +301,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 // Counter block: nonce words 0..2 (folded into cc.p by the
                 // host), word 3 = BE32(counter), whose byte 3 varies.
                 const uint32_t ctr_first = p.ctr0 - p.voff + uint32_t(base) + wave_first * BPL;
-                const uint32_t w3u = bswap32(ctr_first) ^ p.cc.kvar;
+                w3u = bswap32(ctr_first) ^ p.cc.kvar;
                 r1 = p.cc.p[0];
                 u1 = p.cc.p[1] ^ tab_u(te, 2, byte_of(w3u, 2));
                 u2 = p.cc.p[2] ^ tab_u(te, 1, byte_of(w3u, 1));
@@ -330,7 +329,6 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         }
 #pragma unroll
         for (int j = 0; j < BPL; ++j) {
-            const uint64_t idx = block_index<kWM, BPL>(base, j, p.voff);
             if constexpr (OP == Op::kEcbEnc || OP == Op::kEcbDec || OP == Op::kCbcDec) {
                 s[j][0] = in[j].x ^ p.rk.w[0];
                 s[j][1] = in[j].y ^ p.rk.w[1];
@@ -340,7 +338,11 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 // Round-1 word 0: the one per-block lookup of round 1.
                 uint32_t v0;
                 if constexpr (OP == Op::kCtrBe32) {
-                    const uint32_t w3 = bswap32(p.ctr0 + uint32_t(idx)) ^ p.cc.kvar;
+                    // Slot j of lane L has counter ctr_first + 64 j + L, and
+                    // ctr_first is a multiple of 64 * BPL > 64 j + L: the sum
+                    // only sets low bits of the counter's low byte, which is
+                    // byte 3 of the big-endian word.
+                    const uint32_t w3 = w3u ^ ((uint32_t(j) * 64u + (threadIdx.x & 63u)) << 24);
                     v0 = r1 ^ tlook<3>(lds, w3, b.t[3]);
                 } else {
                     const uint32_t w0 = (y0 | tile_slot<true, BPL>(j) % (64u * BPL)) ^ p.cc.kvar;
