@@ -79,8 +79,9 @@ typedef struct {
  * their inverses and the S-boxes on the host and copies them to the device
  * once (the paper's section 3 creates all resources once at start-up).
  * *out receives the context.  The single-buffer calls choose their blocks per
- * lane by size; the environment variable AESGPU_FORCE_BPL=1, 2 or 4, read
- * here, fixes it for this context's calls (for tests and measurements).
+ * lane by size (and CBC decryption with 192- or 256-bit keys takes at most 2);
+ * the environment variable AESGPU_FORCE_BPL=1, 2 or 4, read here, fixes it
+ * for this context's calls (for tests and measurements).
  * Errors: EINVAL (out NULL, bad device), ENOMEM, EHIP.
  */
 int aesgpu_create(aesgpu_ctx **out, int device);
