@@ -133,6 +133,7 @@ int run(aesgpu_ctx *ctx, const LaunchArgs &a, aesgpu_stream_t stream) {
     if (!g.ok()) return AESGPU_EHIP;
     LaunchArgs b = a;
     b.bpl = ctx->blocks_per_lane;
+    b.max_tiles = ctx->max_tiles;
     return launch(ctx->d_tables, ctx->n_cu, b, reinterpret_cast<hipStream_t>(stream));
 }
 
@@ -230,7 +231,14 @@ int aesgpu_create(aesgpu_ctx **out, int device) {
         const int v = std::atoi(e);
         if (v == 1 || v == 2 || v == 4) bpl = v;
     }
-    aesgpu_ctx *ctx = new (std::nothrow) aesgpu_ctx{device, n_cu, nullptr, bpl};
+    // AESGPU_MAX_TILES_PER_CU=2..4096 splits single-buffer calls into launches
+    // of fewer tiles (tests use it to cover the split on small buffers).
+    uint32_t max_tiles = 0;
+    if (const char *e = std::getenv("AESGPU_MAX_TILES_PER_CU")) {
+        const long v = std::atol(e);
+        if (v >= 2 && v <= long(kMaxTilesPerCu)) max_tiles = uint32_t(v);
+    }
+    aesgpu_ctx *ctx = new (std::nothrow) aesgpu_ctx{device, n_cu, nullptr, bpl, max_tiles};
     if (!ctx) return AESGPU_ENOMEM;
     const HostTables &t = host_tables();
     if (hipMalloc(&ctx->d_tables, sizeof(t.words)) != hipSuccess) {

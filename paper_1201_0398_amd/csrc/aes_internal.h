@@ -64,7 +64,14 @@ struct LaunchArgs {
     uint32_t iv[4];       // kCtrLe128 (counter of block 0), kCbcDec (IV words)
     uint64_t index0;      // kCtrLe128: added to iv (0 from the host's own calls)
     int bpl;              // blocks per lane: 1, 2 or 4, or 0 to choose by size
+    uint32_t max_tiles;   // most tiles per CU in one kernel launch (a longer call is
+                          // split), 0 = kMaxTilesPerCu
 };
+
+// A single-buffer kernel's workgroup hands out at most 16 * kMaxTilesPerCu
+// shares of work from a 16-bit LDS count; longer calls are split into several
+// launches.
+constexpr uint32_t kMaxTilesPerCu = 4096;
 
 // Enqueues the kernel for `a` on `stream`; returns an AESGPU status.
 int launch(const uint32_t *d_tables, int n_cu, const LaunchArgs &a, hipStream_t stream);
@@ -103,4 +110,6 @@ struct aesgpu_ctx {
     uint32_t *d_tables;
     int blocks_per_lane;   // single-buffer launches: 1, 2 or 4 (AESGPU_FORCE_BPL at
                            // create), 0 = chosen by size
+    uint32_t max_tiles;    // single-buffer launches: tiles per CU per launch
+                           // (AESGPU_MAX_TILES_PER_CU at create), 0 = kMaxTilesPerCu
 };

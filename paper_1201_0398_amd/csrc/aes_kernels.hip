@@ -28,9 +28,11 @@
 //  * 1024 threads per workgroup and one workgroup per CU (the tables take the
 //    whole LDS); the grid is at most one workgroup per CU and strides over
 //    tiles of 1024 * BPL blocks.  BPL is 4 when every CU gets a full tile and
-//    smaller for smaller buffers (every slot of a tile is computed); at one
-//    block per lane a small buffer is cut into tiles of 64..1024 blocks, one
-//    per CU, and the waves past a tile's end leave after the table staging.
+//    smaller for smaller buffers; at one block per lane a small buffer is cut
+//    into tiles of 64..1024 blocks, one per CU.
+//  * A tile is cut into 16 shares of 64 * BPL blocks, and a workgroup's waves
+//    take the shares of its tiles in turn from a count in LDS, so that waves
+//    the CU runs faster do more of them.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -55,23 +57,32 @@ struct Params {
     uint32_t voff;          // virtual index = block index + voff (CTR: ctr0 mod 64 * BPL)
     uint32_t tile;          // blocks per tile: kWG * BPL, or a multiple of 64 below kWG
                             // for small buffers at 1 block per lane
+    uint32_t n_tiles;       // tiles in the launch: ceil((n_full + voff) / tile)
+    uint32_t prev_in;       // CBC: 1 if block -1 (in[-1]) is ciphertext to chain from
+                            // (a later part of a split call), 0 if block 0 takes the IV
     uint32_t iv[4];
     CtrConsts cc;
     RoundKeys rk;
 };
 
-// Position of slot j of this lane inside a tile of kWG * BPL blocks:
-// slot-major (slot j of the workgroup is kWG consecutive blocks) or wave-major
-// (wave w holds the 64 * BPL consecutive blocks from 64 * BPL * w, its slot j
-// the 64 from 64 * j there).  Either way a wave's load or store instruction
-// covers 64 consecutive blocks, 1 KiB.  (With each lane holding BPL
-// consecutive blocks instead, an instruction touches 32 cache lines rather
-// than 8: AES-128 ECB decryption ran 3% slower so.)
+// A tile of kWG * BPL blocks is cut into 16 shares of 64 * BPL blocks, one
+// wave's work.  Position of slot j of this lane when its wave computes share w:
+// slot-major (slot j of the tile is kWG consecutive blocks, share w its 64
+// from 64 * w) or wave-major (share w is the 64 * BPL consecutive blocks from
+// 64 * BPL * w, its slot j the 64 from 64 * j there).  Either way a wave's
+// load or store instruction covers 64 consecutive blocks, 1 KiB.  (With each
+// lane holding BPL consecutive blocks instead, an instruction touches 32 cache
+// lines rather than 8: AES-128 ECB decryption ran 3% slower so.)
 template <bool kWaveMajor, int BPL>
-__device__ __forceinline__ uint32_t tile_slot(int j) {
-    return kWaveMajor ? (threadIdx.x & ~63u) * BPL + uint32_t(j) * 64u + (threadIdx.x & 63u)
-                      : uint32_t(j) * kWG + threadIdx.x;
+__device__ __forceinline__ uint32_t tile_slot(uint32_t w, int j) {
+    const uint32_t lane = threadIdx.x & 63u;
+    return kWaveMajor ? w * (64u * BPL) + uint32_t(j) * 64u + lane
+                      : uint32_t(j) * kWG + w * 64u + lane;
 }
+
+// Lowest position of share w in its tile.
+template <bool kWaveMajor, int BPL>
+constexpr uint32_t kShareStep = kWaveMajor ? 64u * BPL : 64u;
 
 // Buffer resources for the tile at virtual position base, so that every lane
 // issues its loads and stores without a branch and the compiler can place
@@ -82,20 +93,22 @@ __device__ __forceinline__ uint32_t tile_slot(int j) {
 struct TileView {
     rsrc_t in, out;
     uint32_t shift;   // lanes before block 0 in this tile (first tile only)
+    uint32_t w;       // the share of the tile this wave computes
 };
 
 __device__ __forceinline__ TileView tile_view(const uint4 *in, uint4 *out, uint64_t base,
-                                              uint64_t n_full, uint32_t voff, uint32_t tile) {
+                                              uint32_t w, uint64_t n_full, uint32_t voff,
+                                              uint32_t tile) {
     const uint64_t first = base >= voff ? base - voff : 0;
     const uint32_t shift = base >= voff ? 0u : voff;
     const uint64_t left = first < n_full ? n_full - first : 0;
     const uint32_t bytes = 16u * uint32_t(left < tile ? left : tile);
-    return {buffer_rsrc(in + first, bytes), buffer_rsrc(out + first, bytes), shift};
+    return {buffer_rsrc(in + first, bytes), buffer_rsrc(out + first, bytes), shift, w};
 }
 
 template <bool kWaveMajor, int BPL>
 __device__ __forceinline__ uint32_t lane_offset(const TileView &v, int j) {
-    return (tile_slot<kWaveMajor, BPL>(j) - v.shift) * 16u;
+    return (tile_slot<kWaveMajor, BPL>(v.w, j) - v.shift) * 16u;
 }
 
 template <bool kWaveMajor, int BPL>
@@ -107,6 +120,30 @@ __device__ __forceinline__ void load_tile(uint4 (&v)[BPL], const TileView &t) {
 template <bool kWaveMajor, int BPL>
 __device__ __forceinline__ void store_block(const TileView &t, int j, const uint4 &o) {
     buffer_store16(t.out, lane_offset<kWaveMajor, BPL>(t, j), o);
+}
+
+// The next share for this wave: lane 0 adds one to the workgroup's count in
+// LDS and the old count goes to every lane.  The exec mask is narrowed inside
+// the asm block, which also waits for the result, so the tile loop has no
+// branch.  The count is kept in the high half of its word (in decryption
+// kernels the low half holds an InvS table entry, which the add leaves as it
+// is).  Needs all 64 lanes of the wave active.  No memory clobber: the only
+// LDS data the add shares a word with is read-only, and with the clobber the
+// compiler kept only about five table reads in flight in AES-256 encryption.
+__device__ __forceinline__ uint32_t claim_share(uint32_t *count) {
+    uint32_t old = 0;
+    uint64_t exec_save;
+    const uint32_t addr = uint32_t(reinterpret_cast<uintptr_t>(count));   // LDS offset
+    asm volatile(
+        "s_mov_b64 %1, exec\n\t"
+        "s_mov_b64 exec, 1\n\t"
+        "ds_add_rtn_u32 %0, %2, %3\n\t"
+        "s_waitcnt lgkmcnt(0)\n\t"
+        "s_mov_b64 exec, %1\n\t"
+        "s_nop 4"
+        : "+v"(old), "=&s"(exec_save)
+        : "v"(addr), "v"(0x10000u));
+    return uint32_t(__builtin_amdgcn_readfirstlane(old)) >> 16;
 }
 
 // Lane L gets x of lane L - 1 (a DPP shift of the wave); lane 0 keeps lane0.
@@ -126,18 +163,28 @@ __device__ __forceinline__ uint4 from_lane_63(const uint4 &x) {
                       __builtin_amdgcn_mov_dpp(x.w, 0x13C, 0xf, 0xf, false));
 }
 
-// CBC (wave-major tiles): block first - 1, where first is the wave's first
-// block in the tile at base (the same address in every lane), read through a
-// resource that starts one block before the tile; zero where first == 0 (the
-// caller substitutes the IV) or past the end.
+// CBC (wave-major tiles): block first - 1, where first = base + 64 * BPL * w
+// is the first block of share w of the tile at base (the same address in
+// every lane), read through a resource that starts one block before the tile;
+// zero past the end, and where first == 0 unless block -1 exists (prev_in; if
+// not, the caller substitutes the IV).
 template <int BPL>
-__device__ __forceinline__ uint4 load_wave_prev(const uint4 *in, uint64_t base, uint32_t wave_first,
-                                                uint64_t n_full, uint32_t tile) {
-    const uint64_t start = base > 0 ? base - 1 : 0;
-    const uint32_t shift = base > 0 ? 0u : 1u;
-    const uint64_t left = start < n_full ? n_full - start : 0;
-    const rsrc_t r = buffer_rsrc(in + start, 16u * uint32_t(left < tile + 1u ? left : tile + 1u));
-    return buffer_load16(r, (wave_first * BPL - shift) * 16u);
+__device__ __forceinline__ uint4 load_wave_prev(const uint4 *in, uint64_t base, uint32_t w,
+                                                uint64_t n_full, uint32_t tile, uint32_t prev_in) {
+    const bool before = base > 0 || prev_in;
+    const uint32_t shift = before ? 0u : 1u;
+    // The resource is the same in every lane; the compiler does not see that
+    // through the select and would otherwise load in a loop over lane values.
+    const uint64_t at = reinterpret_cast<uint64_t>(in + base) - 16u * (1u - shift);
+    const uint64_t left = base < n_full ? n_full - base + 1 - shift : 0;
+    const uint32_t bytes = 16u * uint32_t(left < tile + 1u ? left : tile + 1u);
+    // (readfirstlane returns an int: each half is taken as unsigned before it
+    // is widened, or a low word with bit 31 set would fill the high word.)
+    const uint64_t at_u = uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(at)))) |
+                          (uint64_t(uint32_t(__builtin_amdgcn_readfirstlane(uint32_t(at >> 32)))) << 32);
+    const rsrc_t r = buffer_rsrc(reinterpret_cast<const void *>(at_u),
+                                 uint32_t(__builtin_amdgcn_readfirstlane(bytes)));
+    return buffer_load16(r, (w * 64u * BPL - shift) * 16u);
 }
 
 // T_t[x] from the table copy in device memory, for an index that is the same
@@ -196,7 +243,11 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
     constexpr bool kCtr = (OP == Op::kCtrBe32 || OP == Op::kCtrLe128);
     constexpr bool kWM = kCtr || OP == Op::kCbcDec;   // wave-major tiles
-    __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords];
+    // The workgroup's share count: the word after the forward tables, which
+    // in decryption kernels is the first copy of InvS[0] (its high half is
+    // zero after the staging; the InvS entry uses bytes 0 and 1).
+    __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords + 1];
+    uint32_t *const count = lds + kFwdWords;
     // Odd waves issue at a higher priority than even ones (a workgroup's
     // waves go to the CU's four SIMDs in turn, so two SIMDs run high and two
     // low).  The halves then drift out of step: one half's rounds issue table
@@ -209,30 +260,51 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     const uint64_t v_end = p.n_full ? p.n_full + p.voff : 0;
     const uint64_t tile = p.tile;
     const uint64_t stride = uint64_t(gridDim.x) * tile;
-    const uint32_t wave_first = __builtin_amdgcn_readfirstlane(threadIdx.x & ~63u);
-    // The blocks of the next tile are loaded while the current one is
+    // The workgroup's tiles (blockIdx.x, then every gridDim.x-th) are cut into
+    // 16 shares each, numbered in order: share c is share c % 16 of tile
+    // c / 16.  Wave i takes share i first, then the waves claim the next
+    // shares from the count as they finish, so fast waves take more of them:
+    // the CU's arbitration gives its waves very unequal rates (with a fixed
+    // share per wave, the last wave of a workgroup ended up to 2.4 times
+    // later than its first), and claiming evens the waves' end times out.
+    // A share exists if its first position is before the end; shares are
+    // numbered in position order, so the workgroup's shares are 0 .. n_shares
+    // - 1 and a wave's first claim past them is its last.  With at most
+    // 16 * kMaxTilesPerCu shares, the 16-bit count never wraps.
+    auto tile_of = [&](uint32_t c) -> uint64_t {
+        return uint64_t(blockIdx.x) * tile + uint64_t(c >> 4) * stride;
+    };
+    const uint32_t n_tiles_wg =
+        blockIdx.x < p.n_tiles ? (p.n_tiles - 1u - blockIdx.x) / gridDim.x + 1u : 0u;
+    uint32_t n_shares = 0;
+    if (n_tiles_wg) {
+        constexpr uint32_t kStep = kShareStep<kWM, BPL>;
+        const uint64_t left = v_end - tile_of((n_tiles_wg - 1u) << 4);   // > 0
+        n_shares = (n_tiles_wg - 1u) * 16u + uint32_t(std::min<uint64_t>(16, (left + kStep - 1) / kStep));
+    }
+    if constexpr (!kInv)
+        if (threadIdx.x == 0) *count = 0u;   // published by the staging barrier
+    uint32_t cur = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    // The blocks of the next share are loaded while the current one is
     // computed, so HBM latency overlaps the rounds even at low occupancy.
-    // The first tile's loads are issued before the tables are staged, so their
-    // HBM latency overlaps the staging.
+    // The first share's loads are issued before the tables are staged, so
+    // their HBM latency overlaps the staging.
     uint4 next[BPL];
     uint4 next_prev = make_uint4(0, 0, 0, 0);   // CBC only
-    TileView view = tile_view(p.in, p.out, uint64_t(blockIdx.x) * tile, p.n_full, p.voff, tile);
+    TileView view = tile_view(p.in, p.out, tile_of(cur), cur & 15u, p.n_full, p.voff, tile);
     load_tile<kWM, BPL>(next, view);
     if constexpr (OP == Op::kCbcDec) {
-        next_prev = load_wave_prev<BPL>(p.in, uint64_t(blockIdx.x) * tile, wave_first, p.n_full,
-                                        uint32_t(tile));
-        // Block 0 is the first block of wave 0's first tile in workgroup 0,
-        // and no later tile holds it: its predecessor, the IV, is put in here
-        // rather than chosen in the loop.  (Chosen there, it put a branch in
-        // the loop and kept four more SGPRs live, and the compiler kept only
-        // ≈5 table reads in flight per wave instead of ≈17.)
-        if (blockIdx.x == 0 && wave_first == 0)
+        next_prev = load_wave_prev<BPL>(p.in, tile_of(cur), cur & 15u, p.n_full, uint32_t(tile),
+                                        p.prev_in);
+        // Block 0 is the first block of share 0 of workgroup 0, which wave 0
+        // takes first: its predecessor, the IV, is put in here rather than
+        // chosen in the loop.  (Chosen there, it put a branch in the loop and
+        // kept four more SGPRs live, and the compiler kept only ≈5 table reads
+        // in flight per wave instead of ≈17.)
+        if (blockIdx.x == 0 && cur == 0 && !p.prev_in)
             next_prev = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
     }
     stage_tables<kInv>(lds, p.tables);
-    // A small tile leaves the workgroup's last waves without blocks in every
-    // tile: they end here (the staging barrier was the last one).
-    if (wave_first * BPL >= p.tile) return;
     const Bases b = lane_bases();
     // AES-256, and AES-192 CTR and CBC, take their middle rounds' keys from
     // VGPRs by row broadcast (DPP) rather than holding all of them in SGPRs:
@@ -266,23 +338,23 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         for (int j = 0; j < BPL; ++j)
             buffer_store16(none, lane_offset<kWM, BPL>(view, j), make_uint4(0, 0, 0, 0));
     }
-    // A wave leaves the loop at the first tile that has no block for it
-    // (its first slot is its lowest position in a tile): in a grid-stride
-    // launch the last tiles are often partial, and a partial tile of a few
-    // blocks otherwise costs its workgroup a whole tile's rounds.
-    const uint64_t wave_lo = kWM ? uint64_t(wave_first) * BPL : wave_first;
-    for (uint64_t base = uint64_t(blockIdx.x) * tile; base + wave_lo < v_end; base += stride) {
+    // The shares of a partial last tile with no block are not computed: a
+    // partial tile of a few blocks otherwise costs a whole tile's rounds.
+    while (cur < n_shares) {
         uint32_t s[BPL][4];
         uint4 in[BPL];
 #pragma unroll
         for (int j = 0; j < BPL; ++j) in[j] = next[j];
         const uint4 wave_prev = next_prev;
-        const TileView cur = view;
-        view = tile_view(p.in, p.out, base + stride, p.n_full, p.voff, tile);
+        const TileView now = view;
+        const uint64_t base = tile_of(cur);
+        const uint32_t w = cur & 15u;
+        cur = 16u + claim_share(count);
+        view = tile_view(p.in, p.out, tile_of(cur), cur & 15u, p.n_full, p.voff, tile);
         load_tile<kWM, BPL>(next, view);
         if constexpr (OP == Op::kCbcDec)
-            next_prev = load_wave_prev<BPL>(p.in, base + stride, wave_first, p.n_full,
-                                            uint32_t(tile));
+            next_prev = load_wave_prev<BPL>(p.in, tile_of(cur), cur & 15u, p.n_full, uint32_t(tile),
+                                            p.prev_in);
         // CTR rounds 1 and 2.  The wave's 64 * BPL counters start at a
         // multiple of 64 * BPL, so they differ only in their low byte, and so
         // does the whitened counter block.  Round 1 (Eq. (1)): the varying
@@ -300,7 +372,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
             if constexpr (OP == Op::kCtrBe32) {
                 // Counter block: nonce words 0..2 (folded into cc.p by the
                 // host), word 3 = BE32(counter), whose byte 3 varies.
-                const uint32_t ctr_first = p.ctr0 - p.voff + uint32_t(base) + wave_first * BPL;
+                const uint32_t ctr_first = p.ctr0 - p.voff + uint32_t(base) + w * (64u * BPL);
                 w3u = bswap32(ctr_first) ^ p.cc.kvar;
                 r1 = p.cc.p[0];
                 u1 = p.cc.p[1] ^ tab_u(te, 2, byte_of(w3u, 2));
@@ -310,7 +382,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 // Counter block: the 128-bit LE integer whose words 1..3 are
                 // fixed over the launch (folded into cc.p by the host) and
                 // whose word 0 is ctr_y + slot; its byte 0 varies.
-                y0 = p.ctr_y + uint32_t(base) + wave_first * BPL;
+                y0 = p.ctr_y + uint32_t(base) + w * (64u * BPL);
                 const uint32_t s0u = y0 ^ p.cc.kvar;
                 r1 = p.cc.p[0];
                 u1 = p.cc.p[1] ^ tab_u(te, 3, byte_of(s0u, 3));
@@ -345,7 +417,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                     const uint32_t w3 = w3u ^ ((uint32_t(j) * 64u + (threadIdx.x & 63u)) << 24);
                     v0 = r1 ^ tlook<3>(lds, w3, b.t[3]);
                 } else {
-                    const uint32_t w0 = (y0 | tile_slot<true, BPL>(j) % (64u * BPL)) ^ p.cc.kvar;
+                    const uint32_t w0 = (y0 | (uint32_t(j) * 64u + (threadIdx.x & 63u))) ^ p.cc.kvar;
                     v0 = r1 ^ tlook<0>(lds, w0, b.t[0]);
                 }
                 s[j][0] = tlook<0>(lds, v0, b.t[0]) ^ c[0];
@@ -399,7 +471,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
                 o.z ^= q.z;
                 o.w ^= q.w;
             }
-            store_block<kWM, BPL>(cur, j, o);
+            store_block<kWM, BPL>(now, j, o);
         }
     }
     if constexpr (kCtr) {
@@ -423,7 +495,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
 }
 
 template <Op OP, int NR, int BPL>
-int launch_one(Params p, int n_cu, hipStream_t stream) {
+int launch_part(Params p, int n_cu, hipStream_t stream) {
     // CTR: shift the mapping so every wave's 64 * BPL counters start at a
     // multiple of 64 * BPL (so they differ only in their low byte).
     if constexpr (OP == Op::kCtrBe32) {
@@ -450,6 +522,7 @@ int launch_one(Params p, int n_cu, hipStream_t stream) {
     }
     p.tile = uint32_t(tile);
     const uint64_t tiles = (v_end + tile - 1) / tile;
+    p.n_tiles = uint32_t(tiles);
     const uint32_t grid = tiles == 0 ? 1u : uint32_t(tiles < uint64_t(n_cu) ? tiles : uint64_t(n_cu));
     // The launch's own status (the thread's last-error state may hold an
     // earlier, unrelated failure).
@@ -460,18 +533,42 @@ int launch_one(Params p, int n_cu, hipStream_t stream) {
                : AESGPU_EHIP;
 }
 
+// Launches in parts of at most max_tiles - 1 tiles of kWG * BPL blocks per CU,
+// so that a workgroup has at most max_tiles tiles (one more for the CTR shift)
+// and 16 * max_tiles shares.  A part is a whole number of tiles, so the CTR
+// shift is the same in every part; a later CBC part chains from the block
+// before it, and only the last part has the CTR tail.
+template <Op OP, int NR, int BPL>
+int launch_one(const Params &p, int n_cu, uint32_t max_tiles, hipStream_t stream) {
+    const uint64_t part = uint64_t(max_tiles - 1) * uint64_t(n_cu) * uint64_t(kWG) * BPL;
+    Params q = p;
+    for (uint64_t done = 0;; done += part) {
+        const bool last = p.n_full - done <= part;
+        q.in = p.in + done;
+        q.out = p.out + done;
+        q.n_full = last ? p.n_full - done : part;
+        q.tail = last ? p.tail : 0u;
+        q.ctr0 = p.ctr0 + uint32_t(done);
+        q.index0 = p.index0 + done;
+        q.prev_in = done > 0 ? 1u : p.prev_in;
+        const int st = launch_part<OP, NR, BPL>(q, n_cu, stream);
+        if (st != AESGPU_OK || last) return st;
+    }
+}
+
 template <Op OP, int BPL>
-int launch_nr(const Params &p, uint32_t nr, int n_cu, hipStream_t stream) {
+int launch_nr(const Params &p, uint32_t nr, int n_cu, uint32_t max_tiles, hipStream_t stream) {
     switch (nr) {
-        case 10: return launch_one<OP, 10, BPL>(p, n_cu, stream);
-        case 12: return launch_one<OP, 12, BPL>(p, n_cu, stream);
-        case 14: return launch_one<OP, 14, BPL>(p, n_cu, stream);
+        case 10: return launch_one<OP, 10, BPL>(p, n_cu, max_tiles, stream);
+        case 12: return launch_one<OP, 12, BPL>(p, n_cu, max_tiles, stream);
+        case 14: return launch_one<OP, 14, BPL>(p, n_cu, max_tiles, stream);
         default: return AESGPU_EINVAL;
     }
 }
 
 template <Op OP>
-int launch_op(const Params &p, uint32_t nr, int n_cu, int forced_bpl, hipStream_t stream) {
+int launch_op(const Params &p, uint32_t nr, int n_cu, int forced_bpl, uint32_t max_tiles,
+              hipStream_t stream) {
     int bpl = forced_bpl;
     if (bpl != 1 && bpl != 2 && bpl != 4) {
         // Every lane computes all its slots, empty or not, and a workgroup
@@ -492,9 +589,9 @@ int launch_op(const Params &p, uint32_t nr, int n_cu, int forced_bpl, hipStream_
         if (OP == Op::kCbcDec && nr >= 12 && bpl == 4) bpl = 2;
     }
     switch (bpl) {
-        case 1: return launch_nr<OP, 1>(p, nr, n_cu, stream);
-        case 2: return launch_nr<OP, 2>(p, nr, n_cu, stream);
-        default: return launch_nr<OP, 4>(p, nr, n_cu, stream);
+        case 1: return launch_nr<OP, 1>(p, nr, n_cu, max_tiles, stream);
+        case 2: return launch_nr<OP, 2>(p, nr, n_cu, max_tiles, stream);
+        default: return launch_nr<OP, 4>(p, nr, n_cu, max_tiles, stream);
     }
 }
 
@@ -512,12 +609,14 @@ int launch(const uint32_t *d_tables, int n_cu, const LaunchArgs &a, hipStream_t 
     for (int i = 0; i < 4; ++i) p.iv[i] = a.iv[i];
     p.cc = a.ctr;
     p.rk = *a.rk;
+    const uint32_t mt = a.max_tiles >= 2 && a.max_tiles <= kMaxTilesPerCu ? a.max_tiles
+                                                                          : kMaxTilesPerCu;
     switch (a.op) {
-        case Op::kEcbEnc: return launch_op<Op::kEcbEnc>(p, a.nr, n_cu, a.bpl, stream);
-        case Op::kEcbDec: return launch_op<Op::kEcbDec>(p, a.nr, n_cu, a.bpl, stream);
-        case Op::kCtrBe32: return launch_op<Op::kCtrBe32>(p, a.nr, n_cu, a.bpl, stream);
-        case Op::kCtrLe128: return launch_op<Op::kCtrLe128>(p, a.nr, n_cu, a.bpl, stream);
-        case Op::kCbcDec: return launch_op<Op::kCbcDec>(p, a.nr, n_cu, a.bpl, stream);
+        case Op::kEcbEnc: return launch_op<Op::kEcbEnc>(p, a.nr, n_cu, a.bpl, mt, stream);
+        case Op::kEcbDec: return launch_op<Op::kEcbDec>(p, a.nr, n_cu, a.bpl, mt, stream);
+        case Op::kCtrBe32: return launch_op<Op::kCtrBe32>(p, a.nr, n_cu, a.bpl, mt, stream);
+        case Op::kCtrLe128: return launch_op<Op::kCtrLe128>(p, a.nr, n_cu, a.bpl, mt, stream);
+        case Op::kCbcDec: return launch_op<Op::kCbcDec>(p, a.nr, n_cu, a.bpl, mt, stream);
     }
     return AESGPU_EINVAL;
 }
