@@ -57,7 +57,8 @@ struct Params {
     uint32_t voff;          // virtual index = block index + voff (CTR: ctr0 mod 64 * BPL)
     uint32_t tile;          // blocks per tile: kWG * BPL, or a multiple of 64 below kWG
                             // for small buffers at 1 block per lane
-    uint32_t n_tiles;       // tiles in the launch: ceil((n_full + voff) / tile)
+    uint32_t tiles_q;       // tiles in the launch, ceil((n_full + voff) / tile), divided by
+    uint32_t tiles_r;       // the grid size: quotient and remainder
     uint32_t prev_in;       // CBC: 1 if block -1 (in[-1]) is ciphertext to chain from
                             // (a later part of a split call), 0 if block 0 takes the IV
     uint32_t iv[4];
@@ -238,7 +239,10 @@ __device__ __forceinline__ void rounds_v(const uint32_t *lds, const Bases &b, ui
     }
 }
 
-template <Op OP, int NR, int BPL>
+// kDyn: the waves claim the shares of the workgroup's tiles from a count in
+// LDS (launches with several tiles per CU); otherwise wave i computes share i
+// of each of the workgroup's tiles.
+template <Op OP, int NR, int BPL, bool kDyn>
 __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     constexpr bool kInv = (OP == Op::kEcbDec || OP == Op::kCbcDec);
     constexpr bool kCtr = (OP == Op::kCtrBe32 || OP == Op::kCtrLe128);
@@ -246,7 +250,7 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     // The workgroup's share count: the word after the forward tables, which
     // in decryption kernels is the first copy of InvS[0] (its high half is
     // zero after the staging; the InvS entry uses bytes 0 and 1).
-    __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords + 1];
+    __shared__ uint32_t lds[kInv ? kFwdWords + kInvSWords : kFwdWords + (kDyn ? 1 : 0)];
     uint32_t *const count = lds + kFwdWords;
     // Odd waves issue at a higher priority than even ones (a workgroup's
     // waves go to the CU's four SIMDs in turn, so two SIMDs run high and two
@@ -262,8 +266,8 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     const uint64_t stride = uint64_t(gridDim.x) * tile;
     // The workgroup's tiles (blockIdx.x, then every gridDim.x-th) are cut into
     // 16 shares each, numbered in order: share c is share c % 16 of tile
-    // c / 16.  Wave i takes share i first, then the waves claim the next
-    // shares from the count as they finish, so fast waves take more of them:
+    // c / 16.  Wave i takes share i first; with kDyn the waves then claim
+    // the next shares from the count as they finish, so fast waves take more:
     // the CU's arbitration gives its waves very unequal rates (with a fixed
     // share per wave, the last wave of a workgroup ended up to 2.4 times
     // later than its first), and claiming evens the waves' end times out.
@@ -274,17 +278,8 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     auto tile_of = [&](uint32_t c) -> uint64_t {
         return uint64_t(blockIdx.x) * tile + uint64_t(c >> 4) * stride;
     };
-    const uint32_t n_tiles_wg =
-        blockIdx.x < p.n_tiles ? (p.n_tiles - 1u - blockIdx.x) / gridDim.x + 1u : 0u;
-    uint32_t n_shares = 0;
-    if (n_tiles_wg) {
-        constexpr uint32_t kStep = kShareStep<kWM, BPL>;
-        const uint64_t left = v_end - tile_of((n_tiles_wg - 1u) << 4);   // > 0
-        n_shares = (n_tiles_wg - 1u) * 16u + uint32_t(std::min<uint64_t>(16, (left + kStep - 1) / kStep));
-    }
-    if constexpr (!kInv)
-        if (threadIdx.x == 0) *count = 0u;   // published by the staging barrier
-    uint32_t cur = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    uint32_t cur = wave;
     // The blocks of the next share are loaded while the current one is
     // computed, so HBM latency overlaps the rounds even at low occupancy.
     // The first share's loads are issued before the tables are staged, so
@@ -294,17 +289,43 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
     TileView view = tile_view(p.in, p.out, tile_of(cur), cur & 15u, p.n_full, p.voff, tile);
     load_tile<kWM, BPL>(next, view);
     if constexpr (OP == Op::kCbcDec) {
+        // (Launches with one share per wave never chain from block -1, and
+        // with prev_in known to be 0 the compiler kept twice as many table
+        // reads in flight in AES-128 CBC at one block per lane.)
         next_prev = load_wave_prev<BPL>(p.in, tile_of(cur), cur & 15u, p.n_full, uint32_t(tile),
-                                        p.prev_in);
+                                        kDyn ? p.prev_in : 0u);
         // Block 0 is the first block of share 0 of workgroup 0, which wave 0
         // takes first: its predecessor, the IV, is put in here rather than
         // chosen in the loop.  (Chosen there, it put a branch in the loop and
         // kept four more SGPRs live, and the compiler kept only ≈5 table reads
         // in flight per wave instead of ≈17.)
-        if (blockIdx.x == 0 && cur == 0 && !p.prev_in)
+        if (blockIdx.x == 0 && cur == 0 && !(kDyn && p.prev_in))
             next_prev = make_uint4(p.iv[0], p.iv[1], p.iv[2], p.iv[3]);
     }
+    // The share count is worked out after the first loads are issued, and its
+    // kernel arguments are read with theirs: placed before the loads, or read
+    // after the staging, it cost a second round trip for kernel arguments and
+    // a small call (one tile per CU) about 1.3 us.
+    uint32_t n_tiles_wg = p.tiles_q + (blockIdx.x < p.tiles_r ? 1u : 0u);
+    if constexpr (kDyn) {
+        asm volatile("" : "+s"(n_tiles_wg));
+        if constexpr (!kInv)
+            if (threadIdx.x == 0) *count = 0u;   // published by the staging barrier
+    }
     stage_tables<kInv>(lds, p.tables);
+    constexpr uint32_t kStep = kShareStep<kWM, BPL>;
+    uint32_t n_shares = 0;
+    if constexpr (kDyn) {
+        if (n_tiles_wg) {
+            const uint64_t left = v_end - tile_of((n_tiles_wg - 1u) << 4);   // > 0
+            n_shares = (n_tiles_wg - 1u) * 16u +
+                       uint32_t(std::min<uint64_t>(16, (left + kStep - 1) / kStep));
+        }
+    } else {
+        // A small tile leaves the workgroup's last waves without blocks: they
+        // end here (the staging barrier was the last one).
+        if (wave * kStep >= p.tile) return;
+    }
     const Bases b = lane_bases();
     // AES-256, and AES-192 CTR and CBC, take their middle rounds' keys from
     // VGPRs by row broadcast (DPP) rather than holding all of them in SGPRs:
@@ -338,23 +359,20 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
         for (int j = 0; j < BPL; ++j)
             buffer_store16(none, lane_offset<kWM, BPL>(view, j), make_uint4(0, 0, 0, 0));
     }
-    // The shares of a partial last tile with no block are not computed: a
-    // partial tile of a few blocks otherwise costs a whole tile's rounds.
-    while (cur < n_shares) {
+    // One step: share w of the tile at base, while the blocks of share
+    // next_w of the tile at next_base are loaded.
+    auto step = [&](uint64_t base, uint32_t w, uint64_t next_base, uint32_t next_w) {
         uint32_t s[BPL][4];
         uint4 in[BPL];
 #pragma unroll
         for (int j = 0; j < BPL; ++j) in[j] = next[j];
         const uint4 wave_prev = next_prev;
         const TileView now = view;
-        const uint64_t base = tile_of(cur);
-        const uint32_t w = cur & 15u;
-        cur = 16u + claim_share(count);
-        view = tile_view(p.in, p.out, tile_of(cur), cur & 15u, p.n_full, p.voff, tile);
+        view = tile_view(p.in, p.out, next_base, next_w, p.n_full, p.voff, tile);
         load_tile<kWM, BPL>(next, view);
         if constexpr (OP == Op::kCbcDec)
-            next_prev = load_wave_prev<BPL>(p.in, tile_of(cur), cur & 15u, p.n_full, uint32_t(tile),
-                                            p.prev_in);
+            next_prev = load_wave_prev<BPL>(p.in, next_base, next_w, p.n_full, uint32_t(tile),
+                                            kDyn ? p.prev_in : 0u);
         // CTR rounds 1 and 2.  The wave's 64 * BPL counters start at a
         // multiple of 64 * BPL, so they differ only in their low byte, and so
         // does the whitened counter block.  Round 1 (Eq. (1)): the varying
@@ -473,6 +491,21 @@ __global__ __launch_bounds__(kWG) void aes_kernel(Params p) {
             }
             store_block<kWM, BPL>(now, j, o);
         }
+    };
+    // The shares of a partial last tile with no block are not computed: a
+    // partial tile of a few blocks otherwise costs a whole tile's rounds.
+    if constexpr (kDyn) {
+        while (cur < n_shares) {
+            const uint64_t base = tile_of(cur);
+            const uint32_t w = cur & 15u;
+            cur = 16u + claim_share(count);
+            step(base, w, tile_of(cur), cur & 15u);
+        }
+    } else {
+        // A wave leaves the loop at the first tile that has no block for it.
+        for (uint64_t base = uint64_t(blockIdx.x) * tile; base + uint64_t(wave) * kStep < v_end;
+             base += stride)
+            step(base, wave, base + stride, wave);
     }
     if constexpr (kCtr) {
         // Partial last block: wave 0 of workgroup 0 computes its keystream
@@ -522,13 +555,22 @@ int launch_part(Params p, int n_cu, hipStream_t stream) {
     }
     p.tile = uint32_t(tile);
     const uint64_t tiles = (v_end + tile - 1) / tile;
-    p.n_tiles = uint32_t(tiles);
     const uint32_t grid = tiles == 0 ? 1u : uint32_t(tiles < uint64_t(n_cu) ? tiles : uint64_t(n_cu));
+    p.tiles_q = uint32_t(tiles / grid);
+    p.tiles_r = uint32_t(tiles % grid);
+    // With at most one tile per CU the waves have nothing to even out, and a
+    // small call ran about 1.2 us longer with the share count (measured at
+    // 16 KiB .. 1 MiB; at 4 MiB, one tile of 1024 blocks per CU, both took
+    // the same time): such launches at one block per lane keep one share per
+    // wave, unless they are a later part of a split CBC call.
+    const void *kernel = reinterpret_cast<const void *>(&aes_kernel<OP, NR, BPL, true>);
+    if constexpr (BPL == 1)
+        if (tiles <= uint64_t(n_cu) && !p.prev_in)
+            kernel = reinterpret_cast<const void *>(&aes_kernel<OP, NR, BPL, false>);
     // The launch's own status (the thread's last-error state may hold an
     // earlier, unrelated failure).
     void *args[] = {&p};
-    return hipLaunchKernel(reinterpret_cast<const void *>(&aes_kernel<OP, NR, BPL>), dim3(grid),
-                           dim3(kWG), args, 0, stream) == hipSuccess
+    return hipLaunchKernel(kernel, dim3(grid), dim3(kWG), args, 0, stream) == hipSuccess
                ? AESGPU_OK
                : AESGPU_EHIP;
 }

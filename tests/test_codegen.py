@@ -30,8 +30,8 @@ MIN_IN_FLIGHT = {1: 7.0, 2: 10.0, 4: 10.0}
 # and CTR at 4 blocks per lane reload a few words per tile (ECB measured no
 # faster at 2); CBC decryption with AES-192/256 keys launches at 2 blocks per
 # lane instead.
-KNOWN_SPILLS = {("ecb_enc", 14, 4): 12, ("ecb_dec", 14, 4): 28, ("ctr_be32", 14, 4): 8,
-                ("cbc_dec", 12, 4): 104, ("cbc_dec", 14, 4): 80}
+KNOWN_SPILLS = {("ecb_enc", 14, 4): 20, ("ecb_dec", 14, 4): 20, ("ctr_be32", 14, 4): 8,
+                ("cbc_dec", 14, 4): 36}
 
 
 def _asm(src: str, tmp_path) -> list:
@@ -96,10 +96,12 @@ def test_single_buffer_tile_loops(tmp_path):
     lines = _asm("aes_kernels.hip", tmp_path)
     seen = 0
     for name, lo, hi in _kernels(lines):
-        m = re.search(r"aes_kernelILNS_2OpE(\d)ELi(\d+)ELi(\d)E", name)
+        m = re.search(r"aes_kernelILNS_2OpE(\d)ELi(\d+)ELi(\d)ELb(\d)E", name)
         if not m:
             continue
         op, nr, bpl = OPS[m.group(1)], int(m.group(2)), int(m.group(3))
+        if m.group(4) == "0":
+            op += " (one share per wave)"
         seen += 1
         loop = _largest_loop(lines, lo, hi)
         assert loop is not None, f"{op} Nr={nr} {bpl}/lane: no tile loop"
@@ -111,11 +113,13 @@ def test_single_buffer_tile_loops(tmp_path):
         got = _in_flight(body)
         assert got >= MIN_IN_FLIGHT[bpl], \
             f"{op} Nr={nr} {bpl}/lane: {got:.1f} table reads in flight at a wait"
-        assert _scratch(lines, lo, hi) <= KNOWN_SPILLS.get((op, nr, bpl), 0), \
+        assert _scratch(lines, lo, hi) <= KNOWN_SPILLS.get((op.split()[0], nr, bpl), 0), \
             f"{op} Nr={nr} {bpl}/lane spills to scratch"
         signed = [l.strip() for l in lines[lo:hi] if re.match(r"\s+s_(bfe_i64|bfe_i32|ashr_i32|ashr_i64|sext)", l)]
         assert not signed, f"{op} Nr={nr} {bpl}/lane sign-extends: {signed[:3]}"
-    assert seen == 5 * 3 * 3, f"expected 45 single-buffer kernels, found {seen}"
+    # every operation, key size and blocks per lane with shares claimed, and
+    # at one block per lane also with one share per wave
+    assert seen == 5 * 3 * 3 + 5 * 3, f"expected 60 single-buffer kernels, found {seen}"
 
 
 def test_batched_kernels_do_not_spill(tmp_path):
