@@ -81,7 +81,10 @@ typedef struct {
  * *out receives the context.  The single-buffer calls choose their blocks per
  * lane by size (and CBC decryption with 192- or 256-bit keys takes at most 2);
  * the environment variable AESGPU_FORCE_BPL=1, 2 or 4, read here, fixes it
- * for this context's calls (for tests and measurements).
+ * for this context's calls (for tests and measurements).  A single-buffer
+ * call of more than 4095 tiles per CU (about 64 GiB at 4 blocks per lane on
+ * 256 CUs) runs as several launches on the same stream;
+ * AESGPU_MAX_TILES_PER_CU=2..4096, read here, lowers that limit (for tests).
  * Errors: EINVAL (out NULL, bad device), ENOMEM, EHIP.
  */
 int aesgpu_create(aesgpu_ctx **out, int device);
